@@ -1,0 +1,256 @@
+"""Born map, losses and gradients of atomic tomography (FP64 oracle).
+
+Definitions followed (paper, problem-formulation and matrix-free sections):
+
+* atomic density ``rho = sum_r alpha_r |psi_r><psi_r|``       (eq. atomic-density)
+* Born probabilities ``pi_m = tr(E_m rho)``                    (eq. born-map)
+* atom response ``a_m(psi) = <psi|E_m|psi>`` and ``pi = A alpha`` (eqs. atom-response,
+  atomic-born-map)
+* cross-entropy ``L = -sum_m pihat_m log(pi_m + eps)``          (eq. qst-loss)
+* likelihood ratio ``c = pihat / (pi + eps)``                   (eq. likelihood-ratio-vector)
+* weight gradient ``-A^T c``                                    (eq. weight-gradient)
+* atom Wirtinger gradient ``-alpha_r G psi_r``                  (eq. atom-wirtinger-gradient)
+* ``G = sum_m c_m E_m``                                         (eq. negative-gradient-matrix)
+
+Interface convention (the paper stacks all settings into one POVM with the
+factor ``1/B`` inside ``E_{b,u}``):  arrays handed around here are *per
+setting* -- ``p[b, u] = <u|V_b rho V_b^dagger|u>`` and ``f[b, u] = N_{b,u}/N_s``,
+each row summing to one -- and the losses act on the stacked vectors
+``pi = p / B``, ``pihat = f / B``.  For generality every loss is reduced to the
+per-outcome sensitivity ``g[b, u] = dL/dp[b, u]``; the gradients are then
+
+* ``dL/dpsi_r^* = alpha_r sum_b V_b^dagger (g_b * V_b psi_r)``
+* ``dL/dalpha_r = sum_{b,u} g[b, u] |(V_b psi_r)_u|^2``
+
+which for cross-entropy equal ``-alpha_r G psi_r`` and ``-(A^T c)_r``.
+The least-squares loss ``L = 1/2 ||pi - pihat||^2`` is not in the paper; it is
+included as the second loss of the interface.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import pauli
+
+LOSS_CE, LOSS_LS, LOSS_NONE = 0, 1, 2
+
+
+# ---------------------------------------------------------------- densities
+def density(atoms: np.ndarray, weights: np.ndarray) -> np.ndarray:
+    """``rho = Psi diag(alpha) Psi^*`` (eq. atomic-density); ``atoms`` is ``[R][D]``."""
+    atoms = np.asarray(atoms, dtype=np.complex128)
+    w = np.asarray(weights, dtype=np.float64)
+    rho = np.zeros((atoms.shape[1], atoms.shape[1]), dtype=np.complex128)
+    for r in range(atoms.shape[0]):
+        rho += w[r] * np.outer(atoms[r], atoms[r].conj())
+    return rho
+
+
+# ---------------------------------------------------------------- forward
+def probs_dense(atoms, weights, settings) -> np.ndarray:
+    """Per-setting ``p[b,u] = B tr(E_{b,u} rho)`` from dense POVM effects (n <= 4)."""
+    settings = np.asarray(settings)
+    B = settings.shape[0]
+    E = pauli.povm_elements(settings)
+    rho = density(atoms, weights)
+    D = rho.shape[0]
+    p = np.zeros((B, D))
+    for b in range(B):
+        for u in range(D):
+            p[b, u] = B * np.real(np.trace(E[b, u] @ rho))
+    return p
+
+
+def atom_response_dense(atoms, settings) -> np.ndarray:
+    """Stacked atom-response matrix ``A[m, r] = <psi_r|E_m|psi_r>`` (``M = B*D`` rows)."""
+    settings = np.asarray(settings)
+    E = pauli.povm_elements(settings)
+    B, D = E.shape[0], E.shape[1]
+    atoms = np.asarray(atoms, dtype=np.complex128)
+    A = np.zeros((B * D, atoms.shape[0]))
+    for b in range(B):
+        for u in range(D):
+            for r in range(atoms.shape[0]):
+                A[b * D + u, r] = np.real(atoms[r].conj() @ E[b, u] @ atoms[r])
+    return A
+
+
+def probs_kron(atoms, weights, settings) -> np.ndarray:
+    """``p[b,u] = sum_r alpha_r |(V_b psi_r)_u|^2`` with dense ``V_b`` (n <= 12)."""
+    settings = np.asarray(settings)
+    atoms = np.asarray(atoms, dtype=np.complex128)
+    w = np.asarray(weights, dtype=np.float64)
+    p = np.zeros((settings.shape[0], atoms.shape[1]))
+    for b in range(settings.shape[0]):
+        V = pauli.setting_unitary(settings[b])
+        for r in range(atoms.shape[0]):
+            p[b] += w[r] * np.abs(V @ atoms[r]) ** 2
+    return p
+
+
+def rotate_axis(atoms, codes) -> np.ndarray:
+    """``phi_r = V_b psi_r`` for every atom, per-axis contraction (any n)."""
+    return np.stack([pauli.apply_setting_axis(codes, a) for a in np.asarray(atoms)])
+
+
+def probs_axis(atoms, weights, settings, rows=None) -> np.ndarray:
+    """``p[b,u]`` by per-axis contraction; ``rows`` restricts to a subset of settings."""
+    settings = np.asarray(settings)
+    w = np.asarray(weights, dtype=np.float64)
+    rows = range(settings.shape[0]) if rows is None else rows
+    out = []
+    for b in rows:
+        phi = rotate_axis(atoms, settings[b])
+        out.append(np.einsum("r,ru->u", w, np.abs(phi) ** 2))
+    return np.asarray(out)
+
+
+# ---------------------------------------------------------------- losses
+def _sum(x: np.ndarray) -> float:
+    x = np.asarray(x, dtype=np.float64).reshape(-1)
+    return math.fsum(x) if x.size <= (1 << 20) else float(np.sum(x))
+
+
+def loss_and_sensitivity(p, f, B: int, kind: int, eps: float):
+    """Loss on the stacked vectors ``pi = p/B``, ``pihat = f/B`` and ``g = dL/dp``.
+
+    * CE (eq. qst-loss):  ``L = -sum pihat log(pi + eps)``;
+      ``g = -(pihat/(pi+eps))/B = -c/B`` with ``c`` of eq. likelihood-ratio-vector.
+      Outcomes with ``pihat = 0`` contribute nothing (``0 log x = 0``).
+    * LS:  ``L = 1/2 sum (pi - pihat)^2``;  ``g = (pi - pihat)/B``.
+    """
+    p = np.asarray(p, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    pi, pih = p / B, f / B
+    if kind == LOSS_CE:
+        nz = pih > 0
+        terms = np.zeros_like(pi)
+        terms[nz] = -pih[nz] * np.log(pi[nz] + eps)
+        c = np.zeros_like(pi)
+        c[nz] = pih[nz] / (pi[nz] + eps)
+        return _sum(terms), -c / B
+    if kind == LOSS_LS:
+        r = pi - pih
+        return 0.5 * _sum(r * r), r / B
+    raise ValueError("loss kind")
+
+
+def likelihood_ratio(p, f, B: int, eps: float) -> np.ndarray:
+    """``c = pihat / (pi + eps)`` (eq. likelihood-ratio-vector), per setting layout."""
+    p = np.asarray(p, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    return (f / B) / (p / B + eps)
+
+
+# ---------------------------------------------------------------- gradients
+def gradients_dense(atoms, weights, settings, g):
+    """Gradients from dense POVM effects (n <= 4), given ``g = dL/dp`` (per setting).
+
+    With ``dL/dpi_m = B g_m``:  ``dL/dpsi_r^* = alpha_r sum_m (B g_m) E_m psi_r`` and
+    ``dL/dalpha_r = sum_m (B g_m) <psi_r|E_m|psi_r>``.
+    """
+    settings = np.asarray(settings)
+    E = pauli.povm_elements(settings)
+    B, D = E.shape[0], E.shape[1]
+    atoms = np.asarray(atoms, dtype=np.complex128)
+    w = np.asarray(weights, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    R = atoms.shape[0]
+    M = np.zeros((D, D), dtype=np.complex128)
+    for b in range(B):
+        for u in range(D):
+            M += B * g[b, u] * E[b, u]
+    ga = np.stack([w[r] * (M @ atoms[r]) for r in range(R)])
+    gw = np.array([np.real(atoms[r].conj() @ M @ atoms[r]) for r in range(R)])
+    return ga, gw
+
+
+def gradient_matrix_dense(settings, g) -> np.ndarray:
+    """``G = -grad_rho L = -sum_m (dL/dpi_m) E_m``; for CE this is ``sum_m c_m E_m``
+    (eqs. density-gradient, negative-gradient-matrix)."""
+    settings = np.asarray(settings)
+    E = pauli.povm_elements(settings)
+    B, D = E.shape[0], E.shape[1]
+    G = np.zeros((D, D), dtype=np.complex128)
+    for b in range(B):
+        for u in range(D):
+            G -= B * g[b, u] * E[b, u]
+    return G
+
+
+def gradients_kron(atoms, weights, settings, g):
+    """Same gradients with dense per-setting ``V_b`` (n <= 12)."""
+    settings = np.asarray(settings)
+    atoms = np.asarray(atoms, dtype=np.complex128)
+    w = np.asarray(weights, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    R, D = atoms.shape
+    ga = np.zeros((R, D), dtype=np.complex128)
+    gw = np.zeros(R)
+    for b in range(settings.shape[0]):
+        V = pauli.setting_unitary(settings[b])
+        for r in range(R):
+            phi = V @ atoms[r]
+            ga[r] += w[r] * (V.conj().T @ (g[b] * phi))
+            gw[r] += np.sum(g[b] * np.abs(phi) ** 2)
+    return ga, gw
+
+
+def gradients_axis(atoms, weights, settings, g, rows=None):
+    """Same gradients by per-axis contraction; ``rows`` selects a subset of settings
+    (``g`` then has one row per selected setting).  The adjoint is a sum over
+    settings, so a subset gives the exact partial sum."""
+    settings = np.asarray(settings)
+    atoms = np.asarray(atoms, dtype=np.complex128)
+    w = np.asarray(weights, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    rows = list(range(settings.shape[0])) if rows is None else list(rows)
+    R, D = atoms.shape
+    ga = np.zeros((R, D), dtype=np.complex128)
+    gw = np.zeros(R)
+    for i, b in enumerate(rows):
+        for r in range(R):
+            phi = pauli.apply_setting_axis(settings[b], atoms[r])
+            ga[r] += w[r] * pauli.apply_setting_axis(settings[b], g[i] * phi, adjoint=True)
+            gw[r] += np.sum(g[i] * np.abs(phi) ** 2)
+    return ga, gw
+
+
+def apply_gradient_matrix_axis(settings, g, v) -> np.ndarray:
+    """Matrix-free ``G v = -sum_b V_b^dagger (g_b * V_b v)`` (eq. negative-gradient-product)."""
+    settings = np.asarray(settings)
+    out = np.zeros(np.asarray(v).shape[0], dtype=np.complex128)
+    for b in range(settings.shape[0]):
+        out -= pauli.apply_setting_axis(settings[b], g[b] * pauli.apply_setting_axis(settings[b], v), adjoint=True)
+    return out
+
+
+def tangent_project(atoms, atom_grad) -> np.ndarray:
+    """``(I - psi_r psi_r^*) grad_r`` per atom (tangent space of the complex sphere,
+    eq. atom-projected-descent-direction; for CE this is ``-d_r``)."""
+    atoms = np.asarray(atoms, dtype=np.complex128)
+    atom_grad = np.asarray(atom_grad, dtype=np.complex128)
+    out = np.empty_like(atom_grad)
+    for r in range(atoms.shape[0]):
+        out[r] = atom_grad[r] - atoms[r] * (atoms[r].conj() @ atom_grad[r])
+    return out
+
+
+# ---------------------------------------------------------------- composite
+def forward_backward(atoms, weights, settings, f, kind: int, eps: float, tier: str = "axis",
+                     grad_p=None):
+    """Loss, per-setting probabilities and both gradients, by the chosen tier.
+
+    If ``grad_p`` is given it is used as ``g`` (generic mode, loss = None)."""
+    settings = np.asarray(settings)
+    B = settings.shape[0]
+    probs = {"dense": probs_dense, "kron": probs_kron, "axis": probs_axis}[tier](atoms, weights, settings)
+    if grad_p is None:
+        L, g = loss_and_sensitivity(probs, f, B, kind, eps)
+    else:
+        L, g = None, np.asarray(grad_p, dtype=np.float64)
+    grads = {"dense": gradients_dense, "kron": gradients_kron, "axis": gradients_axis}[tier]
+    ga, gw = grads(atoms, weights, settings, g)
+    return L, probs, ga, gw
