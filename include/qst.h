@@ -1,0 +1,189 @@
+/*
+ * qst.h -- C ABI of the MI355X (gfx950) hot path of rank-adaptive matrix-free
+ * atomic quantum state tomography.
+ *
+ * Problem statement (paper, problem-formulation section): a state is a convex
+ * combination of pure-state atoms, rho = sum_r alpha_r |psi_r><psi_r| with
+ * alpha on the simplex (eq. atomic-density); it is measured with B Pauli strings
+ * s_b in {X,Y,Z}^N, each a product basis rotation V_b = V_{s_b,1} (x) ... (x)
+ * V_{s_b,N} followed by a computational-basis readout (numerical-test section,
+ * Pauli design).  The library evaluates the descriptor-level measurement
+ * actions of the matrix-free oracle calls (matrix-free section): the atomic
+ * Born map (eq. atomic-born-map), the loss (eq. qst-loss), the likelihood
+ * ratio (eq. likelihood-ratio-vector), the weight gradient (eq.
+ * weight-gradient), the atom Wirtinger gradient (eq. atom-wirtinger-gradient)
+ * and the matrix-free product G v (eq. negative-gradient-product); plus the
+ * coefficient step with pruning (eqs. coefficient-update, truncation-map) and
+ * the spectral refactorisation (eqs. density-proposal .. spectral-selection).
+ *
+ * Conventions (the paper leaves them open; these are the readings used):
+ *   - Qubit j (0-based; qubit 0 is the leftmost Kronecker factor) is bit
+ *     N-1-j of the amplitude index and of the outcome index u.
+ *   - Pauli codes: X = 0, Y = 1, Z = 2.  V_Z = I, V_X = (1/sqrt2)[[1,1],[1,-1]],
+ *     V_Y = (1/sqrt2)[[1,-i],[1,i]]; outcome bit 0 is the +1 eigenvector.
+ *   - Probabilities, frequencies and sensitivities are PER SETTING: row b of
+ *     p sums to one for unit atoms.  Losses act on the stacked vectors
+ *     pi = p/B and pihat = f/B, so for cross-entropy
+ *         L = -sum_{b,u} (f/B) log(p/B + eps),   g = dL/dp = -(f/B)/(p/B+eps)/B,
+ *     and for least squares (not in the paper)
+ *         L = 1/2 sum (p/B - f/B)^2,             g = (p - f)/B^2.
+ *   - Gradients: atom_grad[r] = dL/dpsi_r^* = alpha_r sum_b V_b^dagger (g_b * V_b psi_r)
+ *     (conjugate-Wirtinger form of eq. atom-wirtinger-gradient; for
+ *     cross-entropy it equals -alpha_r G psi_r); weight_grad[r] = dL/dalpha_r
+ *     = sum_{b,u} g_{b,u} |(V_b psi_r)_u|^2 (= -(A^T c)_r for cross-entropy).
+ *   - Atoms and weights are used exactly as given: no renormalisation.
+ *
+ * Memory and ownership: every bulk array is a caller-owned DEVICE pointer
+ * (row-major, densely packed, complex numbers interleaved re,im).  The
+ * library owns only the handle's workspace, which it allocates in
+ * qst_plan (or on first use) and frees in qst_destroy; it never frees or
+ * keeps caller memory beyond a call.  All calls are asynchronous on the
+ * handle's stream; results are valid after the stream is synchronised.
+ *
+ * Errors: every call returns a qst_status.  Arguments are validated before
+ * anything is enqueued; on error nothing is enqueued and the handle's last
+ * error message is set.  Invalid Pauli codes in device memory (values > 2)
+ * cannot be seen by the host: kernels treat them as Z and raise a device
+ * flag that the next call on the handle reports as QST_ERR_NUMERIC.
+ * No C++ exception crosses this interface.  One handle per thread.
+ */
+#ifndef QST_H
+#define QST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QST_OK = 0,
+  QST_ERR_INVALID_ARG = 1, /* null pointer, bad enum, negative size            */
+  QST_ERR_SHAPE = 2,       /* sizes outside the supported range               */
+  QST_ERR_ALIGN = 3,       /* pointer not aligned to its element size         */
+  QST_ERR_UNSUPPORTED = 4, /* valid request this build does not implement     */
+  QST_ERR_DEVICE = 5,      /* HIP runtime error (message in qst_last_error)  */
+  QST_ERR_OOM = 6,         /* workspace allocation failed                     */
+  QST_ERR_NUMERIC = 7,     /* a kernel raised its device flag (bad code)       */
+  QST_ERR_CAPTURE = 8      /* would allocate while the stream is capturing    */
+} qst_status;
+
+typedef enum {
+  QST_LOSS_CE = 0,  /* eps-stabilised cross-entropy (eq. qst-loss)     */
+  QST_LOSS_LS = 1,  /* least squares on the stacked probabilities      */
+  QST_LOSS_NONE = 2 /* no loss: qst_backward takes the caller's dL/dp   */
+} qst_loss;
+
+typedef enum {
+  QST_PATH_AUTO = 0,          /* BUTTERFLY_F32                                        */
+  QST_PATH_BUTTERFLY_F32 = 1, /* staged per-qubit butterflies, complex64 atoms, FP32   */
+  QST_PATH_BUTTERFLY_F64 = 2, /* same kernels in FP64, complex128 atoms                */
+  QST_PATH_PLAIN_F32 = 3,     /* one HBM pass per qubit (reference kernel for speedups) */
+  QST_PATH_TILE_F16 = 4,      /* fused 4-qubit 16x16 tiles on FP16 MFMA, FP32 accumulate */
+  QST_PATH_TILE_BF16 = 5      /* same with BF16 MFMA operands                          */
+} qst_path;
+
+/* One independent tomography instance (the arguments of the paper's problem
+ * statement: atoms, weights, descriptor-level settings, observed frequencies).
+ *   n_qubits  N, 1..20 (D = 2^N)
+ *   rank      R, 1..16 (the atom count R_t)
+ *   n_settings B >= 1
+ *   atoms     [R][D] complex64 (complex128 for QST_PATH_BUTTERFLY_F64), 8-byte
+ *             (16-byte) aligned
+ *   weights   [R] float64 (alpha)
+ *   settings  [B][N] uint8 Pauli codes
+ *   freqs     [B][D] float32 per-setting frequencies N_{b,u}/N_s; may be NULL when
+ *             no loss is requested                                                 */
+typedef struct {
+  int32_t n_qubits;
+  int32_t rank;
+  int32_t n_settings;
+  int32_t reserved;
+  const void* atoms;
+  const double* weights;
+  const uint8_t* settings;
+  const float* freqs;
+} qst_instance;
+
+typedef struct qst_handle qst_handle;
+
+/* Create a handle bound to HIP device `device` and stream `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  *out receives the handle. */
+qst_status qst_create(int device, void* hip_stream, qst_handle** out);
+/* Destroy a handle and free its workspace (waits for its stream first). */
+qst_status qst_destroy(qst_handle* h);
+/* Re-bind the handle to another stream of the same device. */
+qst_status qst_set_stream(qst_handle* h, void* hip_stream);
+/* Static text for a status code. */
+const char* qst_status_string(qst_status s);
+/* Message of the last error on this handle ("" if none); valid until the next call. */
+const char* qst_last_error(const qst_handle* h);
+
+/* Reserve workspace and choose the setting-batch size for these shapes; when
+ * `autotune` is non-zero the candidates are timed on the handle's stream (this
+ * synchronises).  Later calls with shapes that fit the reservation allocate
+ * nothing, so they may be captured into a HIP graph.  Optional: the compute
+ * calls plan implicitly. */
+qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_path path, int autotune);
+
+/* Forward map (eq. atomic-born-map) for n_inst instances.
+ *   probs[i]  [B][D] per-setting probabilities (float32; float64 for the F64 path),
+ *             or NULL (not materialised); `probs` itself may be NULL.
+ *   loss      [n_inst] float64 device array or NULL; requires freqs and loss != NONE.
+ * Outputs are overwritten. */
+qst_status qst_forward(qst_handle* h, const qst_instance* inst, int n_inst, void* const* probs,
+                       double* loss, qst_loss loss_kind, double eps, qst_path path);
+
+/* Fused forward + adjoint: loss, weight gradient and atom gradient in one pass
+ * over the settings (eqs. qst-loss, weight-gradient, atom-wirtinger-gradient).
+ *   grad_p      NULL: g comes from `loss_kind` and freqs.  Otherwise grad_p[i] is the
+ *               caller's dL/dp [B][D] (float32; float64 for the F64 path) and
+ *               loss_kind must be QST_LOSS_NONE (autograd route).
+ *   atom_grad   [i] -> [R][D] complex64 (complex128 for F64), overwritten.
+ *   weight_grad [i] -> [R] float64, overwritten (entry may be NULL).
+ *   loss        [n_inst] float64 or NULL.
+ *   project_tangent  non-zero: atom_grad[r] <- (I - psi_r psi_r^*) atom_grad[r]
+ *               (tangent space of the complex sphere, eq. atom-projected-descent-direction). */
+qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, const void* const* grad_p,
+                        void* const* atom_grad, double* const* weight_grad, double* loss,
+                        qst_loss loss_kind, double eps, int project_tangent, qst_path path);
+
+/* Coefficient step with pruning (eqs. coefficient-update, truncation-map), FP64,
+ * one work-group on the device (no allocation, capturable):
+ *   beta = proj_simplex(alpha + eta_alpha * hvec);  keep = {r : beta_r > tau}
+ *   (if empty, the first maximum);  alpha_out[0..R_out) = beta_keep / sum(beta_keep),
+ *   alpha_out[R_out..R) = 0;  keep_idx[0..R_out) ascending;  *R_out on the device.
+ * hvec is A^T c = -dL/dalpha.  R in 1..1024.  All pointers are device pointers. */
+qst_status qst_reweight_simplex(qst_handle* h, const double* alpha, const double* hvec, int R,
+                                double eta_alpha, double tau, double* alpha_out, int32_t* keep_idx,
+                                int32_t* R_out);
+
+/* Spectral refactorisation of one instance's current state (update rules for the
+ * spectral slots; Theorem 1).  Lanczos on S = rho + eta_rho G, where
+ * G = -sum_m (dL/dpi_m) E_m comes from the current state and freqs (eq.
+ * density-proposal), with products S v = sum_r alpha_r psi_r <psi_r|v> + eta_rho G v
+ * (eq. density-product); k = min(n_lanczos, D) steps from the start vector v0
+ * with full re-orthogonalisation; the top L = min(L_max, k) Ritz pairs; for
+ * s = 1..L the candidate P_tau(proj_{Delta_s}(lambda_1..s), Phi_s) (eq.
+ * spectral-candidates) scored by the proximal surrogate (eq. proximal-surrogate)
+ * without its constant ||S||^2/(2 eta_rho); s* = first minimiser.
+ * Host-orchestrated (synchronises the stream; not capturable).
+ *   v0          [D] complex128 device start vector (the random draw is an input)
+ *   atoms_out   [L_max][D] complex64 (complex128 for F64): rows 0..R_out-1 hold the
+ *               chosen candidate's atoms (Ritz vectors), the rest is zero
+ *   weights_out [L_max] float64 (zeros beyond R_out);  R_out, s_star: one int32 each
+ *   ritz_vals, ritz_resid, q_scores: [L_max] float64 (entries beyond L are zero)
+ * All output pointers are device pointers. */
+qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_kind, double eps,
+                        double eta_rho, double mu, double tau, int L_max, int n_lanczos, const void* v0,
+                        void* atoms_out, double* weights_out, int32_t* R_out, int32_t* s_star,
+                        double* ritz_vals, double* ritz_resid, double* q_scores, qst_path path);
+
+/* Library build information: a static string (architecture, version). */
+const char* qst_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QST_H */

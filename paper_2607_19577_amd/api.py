@@ -1,0 +1,189 @@
+"""Tensor-level binding of the C ABI (same names as include/qst.h).
+
+PyTorch supplies device memory and the stream; these functions only check
+dtypes/shapes, pass raw pointers and allocate the outputs.  All arithmetic of
+the hot path runs in ``libqst.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import (LOSS_CE, LOSS_LS, LOSS_NONE, PATH_AUTO, PATH_BUTTERFLY_F32, PATH_BUTTERFLY_F64, PATH_PLAIN_F32,
+                   PATH_TILE_BF16, PATH_TILE_F16, QSTError, QstInstance)
+
+__all__ = [
+    "Handle", "Instance", "qst_forward", "qst_backward", "qst_reweight_simplex", "qst_refactor", "qst_plan",
+    "LOSS_CE", "LOSS_LS", "LOSS_NONE", "PATH_AUTO", "PATH_BUTTERFLY_F32", "PATH_BUTTERFLY_F64", "PATH_PLAIN_F32",
+    "PATH_TILE_F16", "PATH_TILE_BF16", "QSTError",
+]
+
+_C_OF_PATH = {
+    PATH_AUTO: torch.complex64, PATH_BUTTERFLY_F32: torch.complex64, PATH_BUTTERFLY_F64: torch.complex128,
+    PATH_PLAIN_F32: torch.complex64, PATH_TILE_F16: torch.complex64, PATH_TILE_BF16: torch.complex64,
+}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """Owns a ``qst_handle`` bound to one device and stream (``device=-1``: validation only)."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        self.lib = _lib.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        if device >= 0:
+            s = stream if stream is not None else torch.cuda.current_stream(device)
+            sp = ctypes.c_void_p(s.cuda_stream)
+        else:
+            sp = None
+        _lib.check(self.lib.qst_create(device, sp, ctypes.byref(h)))
+        self.h = h
+
+    def set_stream(self, stream: torch.cuda.Stream) -> None:
+        _lib.check(self.lib.qst_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), self.h)
+
+    def close(self) -> None:
+        if self.h:
+            self.lib.qst_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Instance:
+    """One tomography instance: atoms [R][D] complex, weights [R] float64,
+    settings [B][N] uint8 (X=0, Y=1, Z=2), freqs [B][D] float32 (optional)."""
+
+    atoms: torch.Tensor
+    weights: torch.Tensor
+    settings: torch.Tensor
+    freqs: Optional[torch.Tensor] = None
+
+    @property
+    def shape(self):
+        B, N = self.settings.shape
+        return N, self.atoms.shape[0], B
+
+    def c_struct(self, path: int) -> QstInstance:
+        N, R, B = self.shape
+        want = _C_OF_PATH[path]
+        if self.atoms.dtype != want:
+            raise TypeError(f"atoms must be {want} for path {path}, got {self.atoms.dtype}")
+        if self.weights.dtype != torch.float64 or self.settings.dtype != torch.uint8:
+            raise TypeError("weights must be float64 and settings uint8")
+        if self.freqs is not None and self.freqs.dtype != torch.float32:
+            raise TypeError("freqs must be float32")
+        for t in (self.atoms, self.weights, self.settings, self.freqs):
+            if t is not None and not t.is_contiguous():
+                raise ValueError("all tensors must be contiguous")
+        if self.atoms.dim() != 2 or self.atoms.shape[1] != (1 << N) or self.weights.shape != (R,):
+            raise ValueError("atoms must be [R][2^N] and weights [R]")
+        if self.freqs is not None and tuple(self.freqs.shape) != (B, 1 << N):
+            raise ValueError("freqs must be [B][2^N]")
+        return QstInstance(N, R, B, 0, self.atoms.data_ptr(), self.weights.data_ptr(), self.settings.data_ptr(),
+                           None if self.freqs is None else self.freqs.data_ptr())
+
+
+def _structs(insts: Sequence[Instance], path: int):
+    arr = (QstInstance * len(insts))()
+    for i, inst in enumerate(insts):
+        arr[i] = inst.c_struct(path)
+    return arr
+
+
+def _real_of(path: int):
+    return torch.float64 if path == PATH_BUTTERFLY_F64 else torch.float32
+
+
+def qst_plan(h: Handle, insts: Sequence[Instance], path: int = PATH_AUTO, autotune: bool = False) -> None:
+    arr = _structs(insts, path)
+    _lib.check(h.lib.qst_plan(h.h, arr, len(insts), path, int(autotune)), h.h)
+
+
+def qst_forward(h: Handle, insts: Sequence[Instance], want_probs: bool = True, loss: int = LOSS_NONE,
+                eps: float = 1e-8, path: int = PATH_AUTO):
+    """Returns ``(probs list or None, loss tensor [n] float64 or None)``."""
+    arr = _structs(insts, path)
+    dev = insts[0].atoms.device
+    probs = None
+    pp = None
+    if want_probs:
+        probs = [torch.empty((i.shape[2], 1 << i.shape[0]), dtype=_real_of(path), device=dev) for i in insts]
+        pp = (ctypes.c_void_p * len(insts))(*[p.data_ptr() for p in probs])
+    lt = torch.empty(len(insts), dtype=torch.float64, device=dev) if loss != LOSS_NONE else None
+    _lib.check(h.lib.qst_forward(h.h, arr, len(insts), pp, _ptr(lt), loss, float(eps), path), h.h)
+    return probs, lt
+
+
+def qst_backward(h: Handle, insts: Sequence[Instance], grad_p: Optional[Sequence[torch.Tensor]] = None,
+                 loss: int = LOSS_CE, eps: float = 1e-8, project_tangent: bool = False, path: int = PATH_AUTO,
+                 want_loss: bool = True, out: Optional[List[torch.Tensor]] = None):
+    """Fused forward + adjoint.  Returns ``(loss [n] float64 or None, atom_grads, weight_grads)``."""
+    arr = _structs(insts, path)
+    n = len(insts)
+    dev = insts[0].atoms.device
+    ag = out if out is not None else [torch.empty_like(i.atoms) for i in insts]
+    wg = [torch.empty(i.shape[1], dtype=torch.float64, device=dev) for i in insts]
+    agp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in ag])
+    wgp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in wg])
+    gpp = None
+    if grad_p is not None:
+        for g, i in zip(grad_p, insts):
+            if g.dtype != _real_of(path) or not g.is_contiguous() or tuple(g.shape) != (i.shape[2], 1 << i.shape[0]):
+                raise ValueError("grad_p must be contiguous [B][D] of the path's real type")
+        gpp = (ctypes.c_void_p * n)(*[g.data_ptr() for g in grad_p])
+        loss = LOSS_NONE
+        want_loss = False
+    lt = torch.empty(n, dtype=torch.float64, device=dev) if want_loss else None
+    _lib.check(h.lib.qst_backward(h.h, arr, n, gpp, agp, wgp, _ptr(lt), loss, float(eps), int(project_tangent), path),
+               h.h)
+    return lt, ag, wg
+
+
+def qst_reweight_simplex(h: Handle, alpha: torch.Tensor, hvec: torch.Tensor, eta: float, tau: float):
+    """Coefficient step + pruning on the device.  Returns ``(alpha_out [R], keep_idx [R], R_out [1])``."""
+    R = alpha.numel()
+    out = torch.empty(R, dtype=torch.float64, device=alpha.device)
+    keep = torch.empty(R, dtype=torch.int32, device=alpha.device)
+    rout = torch.empty(1, dtype=torch.int32, device=alpha.device)
+    _lib.check(h.lib.qst_reweight_simplex(h.h, _ptr(alpha), _ptr(hvec), R, float(eta), float(tau), _ptr(out),
+                                          _ptr(keep), _ptr(rout)), h.h)
+    return out, keep, rout
+
+
+def qst_refactor(h: Handle, inst: Instance, loss: int, eps: float, eta_rho: float, mu: float, tau: float, L_max: int,
+                 n_lanczos: int, v0: torch.Tensor, path: int = PATH_AUTO):
+    """Spectral refactorisation (host-orchestrated Lanczos).  Returns a dict of device tensors."""
+    arr = _structs([inst], path)
+    dev = inst.atoms.device
+    D = inst.atoms.shape[1]
+    if v0.dtype != torch.complex128 or v0.numel() != D:
+        raise ValueError("v0 must be complex128 [D]")
+    atoms_out = torch.empty((L_max, D), dtype=inst.atoms.dtype, device=dev)
+    f64 = dict(dtype=torch.float64, device=dev)
+    w_out, rv, rr, qs = (torch.empty(L_max, **f64) for _ in range(4))
+    r_out = torch.empty(1, dtype=torch.int32, device=dev)
+    s_star = torch.empty(1, dtype=torch.int32, device=dev)
+    _lib.check(h.lib.qst_refactor(h.h, arr, loss, float(eps), float(eta_rho), float(mu), float(tau), int(L_max),
+                                  int(n_lanczos), _ptr(v0), _ptr(atoms_out), _ptr(w_out), _ptr(r_out), _ptr(s_star),
+                                  _ptr(rv), _ptr(rr), _ptr(qs), path), h.h)
+    return dict(atoms=atoms_out, weights=w_out, R=r_out, s_star=s_star, ritz_vals=rv, ritz_resid=rr, q_scores=qs)

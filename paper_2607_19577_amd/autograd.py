@@ -1,0 +1,56 @@
+"""torch.autograd wrappers around the HIP forward map and its adjoint.
+
+PyTorch's gradient of a real loss with respect to a complex tensor z is
+dL/dRe z + i dL/dIm z = 2 dL/dz^*, so the conjugate-Wirtinger atom gradient
+returned by the library (eq. atom-wirtinger-gradient convention) is doubled
+here.  Only the inputs are saved: the backward pass recomputes the rotated
+amplitudes setting batch by setting batch instead of storing B*R*D of them.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+class BornMap(torch.autograd.Function):
+    """probs[b, u] = sum_r alpha_r |(V_b psi_r)_u|^2  (per-setting Born probabilities)."""
+
+    @staticmethod
+    def forward(ctx, atoms, weights, settings, handle, path):
+        inst = api.Instance(atoms.detach().contiguous(), weights.detach().contiguous(), settings)
+        probs, _ = api.qst_forward(handle, [inst], want_probs=True, path=path)
+        ctx.save_for_backward(atoms, weights, settings)
+        ctx.handle, ctx.path = handle, path
+        return probs[0]
+
+    @staticmethod
+    def backward(ctx, grad_probs):
+        atoms, weights, settings = ctx.saved_tensors
+        inst = api.Instance(atoms.detach().contiguous(), weights.detach().contiguous(), settings)
+        _, ag, wg = api.qst_backward(ctx.handle, [inst], grad_p=[grad_probs.contiguous()], path=ctx.path)
+        return 2 * ag[0], wg[0], None, None, None
+
+
+class FusedLoss(torch.autograd.Function):
+    """Loss (CE or LS on the stacked probabilities) with its gradients from one fused pass."""
+
+    @staticmethod
+    def forward(ctx, atoms, weights, settings, freqs, handle, loss, eps, path):
+        inst = api.Instance(atoms.detach().contiguous(), weights.detach().contiguous(), settings, freqs)
+        lt, ag, wg = api.qst_backward(handle, [inst], loss=loss, eps=eps, path=path)
+        ctx.save_for_backward(ag[0], wg[0])
+        return lt[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        ag, wg = ctx.saved_tensors
+        return 2 * ag * grad_out.to(ag.real.dtype), wg * grad_out, None, None, None, None, None, None
+
+
+def born_map(atoms, weights, settings, handle, path=api.PATH_AUTO):
+    return BornMap.apply(atoms, weights, settings, handle, path)
+
+
+def fused_loss(atoms, weights, settings, freqs, handle, loss=api.LOSS_CE, eps=1e-8, path=api.PATH_AUTO):
+    return FusedLoss.apply(atoms, weights, settings, freqs, handle, loss, eps, path)

@@ -1,0 +1,921 @@
+// Host side of the C ABI declared in include/qst.h: validation, geometry and
+// workspace planning, the per-batch launch sequence, and the host-orchestrated
+// spectral refactorisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "qst.h"
+#include "qst_internal.hpp"
+
+using qst::Geometry;
+
+struct qst_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  void* ws = nullptr;  // workspace arena (grow-only)
+  size_t ws_bytes = 0;
+  int* dflag = nullptr;  // device flag raised by kernels (bad Pauli code)
+  int* hflag = nullptr;  // pinned host copy
+  hipEvent_t flag_ev = nullptr;
+  bool flag_pending = false;
+  std::map<std::tuple<int, int, int, int>, int> tuned_S;  // (n, R, B, path) -> settings per batch
+};
+
+namespace {
+
+constexpr int G1 = 256;  // first-level reduction width
+
+qst_status set_err(qst_handle* h, qst_status s, const std::string& msg) {
+  if (h) h->last_error = msg;
+  return s;
+}
+
+#define QST_HIP(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return set_err(h, QST_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+  return cs != hipStreamCaptureStatusNone;
+}
+
+qst_status ensure_ws(qst_handle* h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return QST_OK;
+  if (capturing(h->stream))
+    return set_err(h, QST_ERR_CAPTURE, "workspace must grow while the stream is capturing; call qst_plan first");
+  if (h->ws) {
+    hipStreamSynchronize(h->stream);
+    hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  size_t want = bytes + (bytes >> 3);
+  if (hipMalloc(&h->ws, want) != hipSuccess) {
+    h->ws = nullptr;
+    return set_err(h, QST_ERR_OOM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  h->ws_bytes = want;
+  return QST_OK;
+}
+
+int elem_of(qst_path p) { return p == QST_PATH_BUTTERFLY_F64 ? 8 : 4; }
+
+bool path_valid(int p) { return p >= QST_PATH_AUTO && p <= QST_PATH_TILE_BF16; }
+
+qst_path resolve(qst_path p) { return p == QST_PATH_AUTO ? QST_PATH_BUTTERFLY_F32 : p; }
+
+// Geometry of the staged path for (n, R, B).
+qst_status make_geometry(qst_handle* h, int n, int R, int B, int elem, Geometry& g) {
+  g = Geometry{};
+  g.n = n;
+  g.R = R;
+  g.B = B;
+  g.D = 1ll << n;
+  g.elem = elem;
+  const long long cap = elem == 4 ? 16384 : 8192;  // amplitudes one low-stage work-group holds
+  constexpr size_t kLdsMax = 160 * 1024;
+  int n_lo = n;
+  for (; n_lo > 0; --n_lo) {
+    if (((long long)R << n_lo) > cap) continue;
+    g.n_lo = n_lo;
+    g.logv_lo = std::min(5, n_lo);
+    if (qst::lo_lds_bytes(g) <= kLdsMax) break;
+  }
+  if (n_lo < 1) return set_err(h, QST_ERR_SHAPE, "rank too large for the on-chip low stage");
+  g.n_lo = n_lo;
+  g.n_hi = n - n_lo;
+  g.logv_lo = std::min(5, n_lo);
+  if (g.n_hi > 0) {
+    if (elem != 4)
+      return set_err(h, QST_ERR_UNSUPPORTED,
+                     "the FP64 path holds the whole state on chip: needs R * 2^n <= 8192");
+    g.t = std::min(n, 14);
+    g.c = g.t - g.n_hi;
+    const bool ok = (g.t == 14 && g.n_hi <= 10) || (g.t == 13 && g.n_hi <= 3) || (g.t == 12 && g.n_hi <= 2) ||
+                    (g.t == 11 && g.n_hi == 1);
+    if (!ok || g.c < 0 || g.c > g.n_lo)
+      return set_err(h, QST_ERR_UNSUPPORTED,
+                     "n=" + std::to_string(n) + ", R=" + std::to_string(R) + " is outside the tile-stage shapes");
+  }
+  g.cpw = std::min(4, 1 << g.n_hi);
+  g.items_per_setting = (1ll << g.n_hi) / g.cpw;
+  return QST_OK;
+}
+
+int default_S(const Geometry& g) {
+  const long long per = (long long)g.R * g.D * 2 * g.elem;
+  long long s = (2ll << 30) / std::max(per, 1ll);
+  if (s < 1) s = 1;
+  if (s > g.B) s = g.B;
+  if (g.n_hi > 0 && s > 16) s = 16;  // enough to amortise the psi read and the gradient update
+  return (int)s;
+}
+
+struct WsLayout {
+  size_t pc, X, W, part, lvl1, sums, tan, gneg, total;
+};
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+long long nslots_of(const Geometry& g, qst_path path) {
+  if (path == QST_PATH_PLAIN_F32) return (long long)g.B * ((g.D + 255) / 256);
+  return (long long)g.B * g.items_per_setting;
+}
+
+WsLayout layout_ws(const Geometry& g, int S, qst_path path, bool with_gneg, size_t base = 0) {
+  WsLayout L{};
+  size_t o = base;
+  const size_t vec = (size_t)S * g.R * g.D * 2 * g.elem;
+  L.pc = o;
+  o = al256(o + (size_t)g.B * 8);
+  L.X = o;
+  if (g.n_hi > 0 || path == QST_PATH_PLAIN_F32) o = al256(o + vec);
+  L.W = o;
+  if (path != QST_PATH_PLAIN_F32) o = al256(o + vec);
+  L.part = o;
+  o = al256(o + (size_t)(g.R + 1) * nslots_of(g, path) * 8);
+  L.lvl1 = o;
+  o = al256(o + (size_t)(g.R + 1) * G1 * 8);
+  L.sums = o;
+  o = al256(o + (size_t)(g.R + 1) * 8);
+  L.tan = o;
+  o = al256(o + (size_t)g.R * G1 * 2 * 8 + (size_t)g.R * 2 * 8);
+  L.gneg = o;
+  if (with_gneg) o = al256(o + (size_t)g.B * g.D * g.elem);
+  L.total = o;
+  return L;
+}
+
+qst_status check_flag(qst_handle* h) {
+  if (!h->flag_pending) return QST_OK;
+  if (hipEventQuery(h->flag_ev) != hipSuccess) return QST_OK;  // not reached yet: report later
+  h->flag_pending = false;
+  if (*h->hflag) {
+    *h->hflag = 0;
+    qst::launch_fill(h->dflag, sizeof(int), h->stream);
+    return set_err(h, QST_ERR_NUMERIC, "a setting held a Pauli code > 2 (treated as Z)");
+  }
+  return QST_OK;
+}
+
+void post_flag(qst_handle* h) {
+  if (capturing(h->stream)) return;
+  hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  hipEventRecord(h->flag_ev, h->stream);
+  h->flag_pending = true;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+qst_status validate_instance(qst_handle* h, const qst_instance& in, qst_path path, bool need_freqs) {
+  if (path == QST_PATH_TILE_F16 || path == QST_PATH_TILE_BF16)
+    return set_err(h, QST_ERR_UNSUPPORTED, "tile paths are not built into this library");
+  if (in.n_qubits < 1 || in.n_qubits > 20)
+    return set_err(h, QST_ERR_SHAPE, "n_qubits must be in 1..20 (got " + std::to_string(in.n_qubits) + ")");
+  if (in.rank < 1 || in.rank > 16) return set_err(h, QST_ERR_SHAPE, "rank must be in 1..16");
+  if (in.n_settings < 1) return set_err(h, QST_ERR_SHAPE, "n_settings must be >= 1");
+  if (!in.atoms || !in.weights || !in.settings) return set_err(h, QST_ERR_INVALID_ARG, "null atoms/weights/settings");
+  if (need_freqs && !in.freqs) return set_err(h, QST_ERR_INVALID_ARG, "freqs required for the requested loss");
+  const size_t ea = path == QST_PATH_BUTTERFLY_F64 ? 16 : 8;
+  if (!aligned(in.atoms, ea) || !aligned(in.weights, 8) || (in.freqs && !aligned(in.freqs, 4)))
+    return set_err(h, QST_ERR_ALIGN, "atoms/weights/freqs not aligned to their element size");
+  return QST_OK;
+}
+
+// Enqueue the forward (adjoint=false) or fused forward+adjoint pipeline of one instance.
+struct RunSpec {
+  const qst_instance* in;
+  qst_path path;
+  qst_loss loss_kind;
+  double eps;
+  void* probs;
+  double* loss;
+  const void* grad_p;
+  void* atom_grad;
+  double* weight_grad;
+  int project_tangent;
+  void* gneg;  // optional: receives -dL/dp
+  bool adjoint;
+  int S_override;
+};
+
+qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, size_t* ws_end = nullptr) {
+  const qst_instance& in = *rs.in;
+  const qst_path path = rs.path;
+  Geometry g;
+  qst_status st = make_geometry(h, in.n_qubits, in.rank, in.n_settings, elem_of(path), g);
+  if (st != QST_OK) return st;
+  int S = rs.S_override > 0 ? std::min(rs.S_override, g.B) : default_S(g);
+  {
+    auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)path));
+    if (rs.S_override <= 0 && it != h->tuned_S.end()) S = std::min(it->second, g.B);
+  }
+  g.S = S;
+  const WsLayout L = layout_ws(g, S, path, false, ws_base);
+  if (ws_end) *ws_end = L.total;
+  st = ensure_ws(h, L.total);
+  if (st != QST_OK) return st;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(h->ws);
+  uint64_t* pc = reinterpret_cast<uint64_t*>(ws + L.pc);
+  void* X = ws + L.X;
+  void* W = ws + L.W;
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  double* lvl1 = reinterpret_cast<double*>(ws + L.lvl1);
+  double* sums = reinterpret_cast<double*>(ws + L.sums);
+  hipStream_t s = h->stream;
+
+  QST_HIP(qst::launch_decode(in.settings, g.B, g.n, pc, h->dflag, s));
+  const bool want_loss = rs.grad_p == nullptr && rs.loss_kind != QST_LOSS_NONE;
+  const long long nslots = nslots_of(g, path);
+
+  qst::LoArgs la{};
+  la.pc = pc;
+  la.alpha = in.weights;
+  la.freqs = in.freqs;
+  la.grad_p = rs.grad_p;
+  la.probs = rs.probs;
+  la.gneg = rs.gneg;
+  la.part = (want_loss || rs.adjoint) ? part : nullptr;
+  la.nslots = nslots;
+  la.D = g.D;
+  la.R = g.R;
+  la.n = g.n;
+  la.n_lo = g.n_lo;
+  la.n_hi = g.n_hi;
+  la.log_ta = g.n_lo - g.logv_lo;
+  la.cpw = g.cpw;
+  la.B = g.B;
+  la.loss_kind = rs.grad_p ? 2 : (int)rs.loss_kind;
+  la.eps = rs.eps;
+
+  for (int b0 = 0; b0 < g.B; b0 += S) {
+    const int Sb = std::min(S, g.B - b0);
+    la.b0 = b0;
+    if (path == QST_PATH_PLAIN_F32) {
+      QST_HIP(qst::launch_plain_copy(in.atoms, X, Sb, g.R, g.D, s));
+      for (int bit = 0; bit < g.n; ++bit) QST_HIP(qst::launch_plain_qubit(X, Sb, g.R, g.D, bit, pc, b0, false, s));
+      QST_HIP(qst::launch_plain_point(la, X, Sb, s));
+      if (rs.adjoint) {
+        for (int bit = 0; bit < g.n; ++bit) QST_HIP(qst::launch_plain_qubit(X, Sb, g.R, g.D, bit, pc, b0, true, s));
+        QST_HIP(qst::launch_plain_sum(X, Sb, g.R, g.D, rs.atom_grad, b0 == 0, s));
+      }
+      continue;
+    }
+    const bool tile = path == QST_PATH_TILE_F16 || path == QST_PATH_TILE_BF16;
+    const bool bf16 = path == QST_PATH_TILE_BF16;
+    if (g.n_hi > 0) {
+      qst::HiArgs ha{};
+      ha.src = in.atoms;
+      ha.dst = X;
+      ha.pc = pc;
+      ha.D = g.D;
+      ha.R = g.R;
+      ha.n = g.n;
+      ha.n_lo = g.n_lo;
+      ha.n_hi = g.n_hi;
+      ha.t = g.t;
+      ha.c = g.c;
+      ha.b0 = b0;
+      ha.S = Sb;
+      ha.first = 0;
+      QST_HIP(tile ? qst::launch_tile_hi(g, ha, false, bf16, s) : qst::launch_stage_hi(g, ha, false, s));
+      la.src = X;
+      la.src_set_stride = (long long)g.R * g.D;
+    } else {
+      la.src = in.atoms;
+      la.src_set_stride = 0;
+    }
+    la.dst = W;
+    QST_HIP(tile ? qst::launch_tile_lo(g, la, Sb, rs.adjoint, bf16, s) : qst::launch_stage_lo(g, la, Sb, rs.adjoint, s));
+    if (rs.adjoint) {
+      if (g.n_hi > 0) {
+        qst::HiArgs hc{};
+        hc.src = W;
+        hc.dst = rs.atom_grad;
+        hc.pc = pc;
+        hc.D = g.D;
+        hc.R = g.R;
+        hc.n = g.n;
+        hc.n_lo = g.n_lo;
+        hc.n_hi = g.n_hi;
+        hc.t = g.t;
+        hc.c = g.c;
+        hc.b0 = b0;
+        hc.S = Sb;
+        hc.first = b0 == 0;
+        QST_HIP(tile ? qst::launch_tile_hi(g, hc, true, bf16, s) : qst::launch_stage_hi(g, hc, true, s));
+      } else {
+        QST_HIP(qst::launch_sum_settings(g, W, Sb, rs.atom_grad, b0 == 0, s));
+      }
+    }
+  }
+  if (want_loss || rs.adjoint) {
+    const int rows = rs.adjoint ? g.R + 1 : 1;
+    QST_HIP(qst::launch_rowsum(part, rows, nslots, lvl1, G1, sums, s));
+    if (!want_loss) {
+      // rows 1..R only are meaningful; scatter without the loss
+      QST_HIP(qst::launch_scatter_results(sums, rs.adjoint ? g.R : 0, nullptr, rs.adjoint ? rs.weight_grad : nullptr, s));
+    } else {
+      QST_HIP(qst::launch_scatter_results(sums, rs.adjoint ? g.R : 0, rs.loss, rs.adjoint ? rs.weight_grad : nullptr, s));
+    }
+  }
+  if (rs.adjoint && rs.project_tangent) {
+    QST_HIP(qst::launch_tangent(g.elem, in.atoms, rs.atom_grad, g.R, g.D, reinterpret_cast<double*>(ws + L.tan), G1, s));
+  }
+  return QST_OK;
+}
+
+// ---------------------------------------------------------------- small dense helpers (host FP64)
+// Cyclic Jacobi eigenvalue iteration for a real symmetric k x k matrix (row-major).
+// Returns eigenvalues in w and eigenvectors as columns of V.
+void jacobi_eigh(std::vector<double> A, int k, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) {
+        const double a = A[(size_t)i * k + j];
+        tot += a * a;
+        if (i != j) off += a * a;
+      }
+    if (off <= 1e-30 * std::max(tot, 1e-300)) break;
+    for (int p = 0; p < k - 1; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[(size_t)p * k + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = A[(size_t)p * k + p], aqq = A[(size_t)q * k + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int r = 0; r < k; ++r) {  // A <- J^T A J
+          const double arp = A[(size_t)r * k + p], arq = A[(size_t)r * k + q];
+          A[(size_t)r * k + p] = c * arp - sn * arq;
+          A[(size_t)r * k + q] = sn * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double apr = A[(size_t)p * k + r], aqr = A[(size_t)q * k + r];
+          A[(size_t)p * k + r] = c * apr - sn * aqr;
+          A[(size_t)q * k + r] = sn * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = V[(size_t)r * k + p], vrq = V[(size_t)r * k + q];
+          V[(size_t)r * k + p] = c * vrp - sn * vrq;
+          V[(size_t)r * k + q] = sn * vrp + c * vrq;
+        }
+      }
+  }
+  w.resize(k);
+  for (int i = 0; i < k; ++i) w[i] = A[(size_t)i * k + i];
+}
+
+// Euclidean projection onto the simplex (sort-based), FP64.
+std::vector<double> proj_simplex(const std::vector<double>& v) {
+  std::vector<double> u = v;
+  std::sort(u.begin(), u.end(), [](double a, double b) { return a > b; });
+  double css = 0.0, theta = 0.0;
+  for (size_t j = 0; j < u.size(); ++j) {
+    css += u[j];
+    const double t = (css - 1.0) / (double)(j + 1);
+    if (u[j] - t > 0) theta = t;
+  }
+  std::vector<double> out(v.size());
+  for (size_t i = 0; i < v.size(); ++i) out[i] = std::max(v[i] - theta, 0.0);
+  return out;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+const char* qst_status_string(qst_status s) {
+  switch (s) {
+    case QST_OK: return "ok";
+    case QST_ERR_INVALID_ARG: return "invalid argument";
+    case QST_ERR_SHAPE: return "unsupported shape";
+    case QST_ERR_ALIGN: return "misaligned pointer";
+    case QST_ERR_UNSUPPORTED: return "unsupported request";
+    case QST_ERR_DEVICE: return "HIP runtime error";
+    case QST_ERR_OOM: return "out of device memory";
+    case QST_ERR_NUMERIC: return "numeric fault flagged by a kernel";
+    case QST_ERR_CAPTURE: return "allocation requested during stream capture";
+  }
+  return "unknown status";
+}
+
+const char* qst_build_info(void) { return "qst gfx950 staged-butterfly/tile v1"; }
+
+const char* qst_last_error(const qst_handle* h) { return h ? h->last_error.c_str() : "null handle"; }
+
+qst_status qst_create(int device, void* hip_stream, qst_handle** out) {
+  if (!out) return QST_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (device == -1) {  // validation-only handle: argument checks run, nothing is enqueued
+    qst_handle* h = new qst_handle();
+    h->device = -1;
+    *out = h;
+    return QST_OK;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return QST_ERR_DEVICE;
+  if (device < 0 || device >= ndev) return QST_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return QST_ERR_DEVICE;
+  qst_handle* h = new qst_handle();
+  h->device = device;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipMalloc(&h->dflag, sizeof(int)) != hipSuccess || hipHostMalloc(&h->hflag, sizeof(int)) != hipSuccess ||
+      hipEventCreateWithFlags(&h->flag_ev, hipEventDisableTiming) != hipSuccess) {
+    delete h;
+    return QST_ERR_DEVICE;
+  }
+  *h->hflag = 0;
+  hipMemset(h->dflag, 0, sizeof(int));
+  hipDeviceSynchronize();
+  *out = h;
+  return QST_OK;
+}
+
+qst_status qst_destroy(qst_handle* h) {
+  if (!h) return QST_ERR_INVALID_ARG;
+  if (h->device < 0) {
+    delete h;
+    return QST_OK;
+  }
+  hipSetDevice(h->device);
+  hipStreamSynchronize(h->stream);
+  if (h->ws) hipFree(h->ws);
+  if (h->dflag) hipFree(h->dflag);
+  if (h->hflag) hipHostFree(h->hflag);
+  if (h->flag_ev) hipEventDestroy(h->flag_ev);
+  delete h;
+  return QST_OK;
+}
+
+qst_status qst_set_stream(qst_handle* h, void* hip_stream) {
+  if (!h) return QST_ERR_INVALID_ARG;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return QST_OK;
+}
+
+static qst_status common_checks(qst_handle* h, const qst_instance* inst, int n_inst, qst_path path) {
+  if (!h) return QST_ERR_INVALID_ARG;
+  h->last_error.clear();
+  if (!inst || n_inst < 1) return set_err(h, QST_ERR_INVALID_ARG, "no instances");
+  if (!path_valid(path)) return set_err(h, QST_ERR_INVALID_ARG, "bad path");
+  if (h->device < 0) return QST_OK;
+  if (hipSetDevice(h->device) != hipSuccess) return set_err(h, QST_ERR_DEVICE, "hipSetDevice failed");
+  return check_flag(h);
+}
+
+// After validation: a validation-only handle stops here.
+static qst_status device_gate(qst_handle* h) {
+  if (h->device < 0) return set_err(h, QST_ERR_UNSUPPORTED, "validation-only handle (device -1): arguments are valid");
+  return QST_OK;
+}
+
+qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_path path, int autotune) {
+  qst_status st = common_checks(h, inst, n_inst, path);
+  if (st != QST_OK) return st;
+  path = resolve(path);
+  size_t need = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    st = validate_instance(h, inst[i], path, false);
+    if (st != QST_OK) return st;
+    Geometry g;
+    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, elem_of(path), g);
+    if (st != QST_OK) return st;
+    int S = default_S(g);
+    if (h->device < 0) continue;
+    if (autotune && path != QST_PATH_PLAIN_F32 && g.n_hi > 0) {
+      // Time the fused pass on a slice of the settings for each candidate batch size.
+      const int cands[] = {2, 4, 8, 16, 32};
+      const int B_try = std::min(g.B, 64);
+      qst_instance sub = inst[i];
+      sub.n_settings = B_try;
+      void* grad = nullptr;
+      if (hipMalloc(&grad, (size_t)g.R * g.D * 2 * g.elem) != hipSuccess)
+        return set_err(h, QST_ERR_OOM, "autotune scratch");
+      std::vector<double> wg_dummy;
+      double* wg = nullptr;
+      hipMalloc(&wg, (size_t)g.R * 8 + 8);
+      float best = 1e30f;
+      int best_S = S;
+      hipEvent_t e0, e1;
+      hipEventCreate(&e0);
+      hipEventCreate(&e1);
+      for (int cS : cands) {
+        if (cS > B_try) break;
+        if ((size_t)cS * g.R * g.D * 2 * g.elem > (4ull << 30)) break;
+        RunSpec rs{};
+        rs.in = &sub;
+        rs.path = path;
+        rs.loss_kind = inst[i].freqs ? QST_LOSS_CE : QST_LOSS_NONE;
+        rs.eps = 1e-8;
+        rs.atom_grad = grad;
+        rs.weight_grad = wg;
+        rs.loss = wg + g.R;
+        rs.adjoint = true;
+        rs.S_override = cS;
+        std::vector<float> times;
+        for (int rep = 0; rep < 3; ++rep) {
+          hipEventRecord(e0, h->stream);
+          st = run_instance(h, rs);
+          hipEventRecord(e1, h->stream);
+          if (st != QST_OK) break;
+          hipEventSynchronize(e1);
+          float ms = 0;
+          hipEventElapsedTime(&ms, e0, e1);
+          times.push_back(ms);
+        }
+        if (st != QST_OK) break;
+        std::sort(times.begin(), times.end());
+        if (times[1] < best) {
+          best = times[1];
+          best_S = cS;
+        }
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      hipFree(grad);
+      hipFree(wg);
+      if (st != QST_OK) return st;
+      S = best_S;
+      h->tuned_S[std::make_tuple(g.n, g.R, g.B, (int)path)] = S;
+    }
+    need = std::max(need, layout_ws(g, std::min(S, g.B), path, false).total);
+  }
+  st = device_gate(h);
+  if (st != QST_OK) return st;
+  return ensure_ws(h, need);
+}
+
+qst_status qst_forward(qst_handle* h, const qst_instance* inst, int n_inst, void* const* probs, double* loss,
+                       qst_loss loss_kind, double eps, qst_path path) {
+  qst_status st = common_checks(h, inst, n_inst, path);
+  if (st != QST_OK) return st;
+  path = resolve(path);
+  if (loss_kind < QST_LOSS_CE || loss_kind > QST_LOSS_NONE) return set_err(h, QST_ERR_INVALID_ARG, "bad loss kind");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return set_err(h, QST_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  if (loss && loss_kind == QST_LOSS_NONE) return set_err(h, QST_ERR_INVALID_ARG, "loss requested with QST_LOSS_NONE");
+  for (int i = 0; i < n_inst; ++i) {
+    st = validate_instance(h, inst[i], path, loss != nullptr);
+    if (st != QST_OK) return st;
+    Geometry g;
+    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, elem_of(path), g);
+    if (st != QST_OK) return st;
+  }
+  st = device_gate(h);
+  if (st != QST_OK) return st;
+  for (int i = 0; i < n_inst; ++i) {
+    RunSpec rs{};
+    rs.in = &inst[i];
+    rs.path = path;
+    rs.loss_kind = loss ? loss_kind : QST_LOSS_NONE;
+    rs.eps = eps;
+    rs.probs = probs ? probs[i] : nullptr;
+    rs.loss = loss ? loss + i : nullptr;
+    rs.adjoint = false;
+    st = run_instance(h, rs);
+    if (st != QST_OK) return st;
+  }
+  post_flag(h);
+  return QST_OK;
+}
+
+qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, const void* const* grad_p,
+                        void* const* atom_grad, double* const* weight_grad, double* loss, qst_loss loss_kind,
+                        double eps, int project_tangent, qst_path path) {
+  qst_status st = common_checks(h, inst, n_inst, path);
+  if (st != QST_OK) return st;
+  path = resolve(path);
+  if (loss_kind < QST_LOSS_CE || loss_kind > QST_LOSS_NONE) return set_err(h, QST_ERR_INVALID_ARG, "bad loss kind");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return set_err(h, QST_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  if (!atom_grad) return set_err(h, QST_ERR_INVALID_ARG, "atom_grad required");
+  if (grad_p && loss_kind != QST_LOSS_NONE)
+    return set_err(h, QST_ERR_INVALID_ARG, "grad_p given: loss_kind must be QST_LOSS_NONE");
+  if (!grad_p && loss_kind == QST_LOSS_NONE) return set_err(h, QST_ERR_INVALID_ARG, "no loss and no grad_p");
+  if (grad_p && loss) return set_err(h, QST_ERR_INVALID_ARG, "loss requested with grad_p");
+  for (int i = 0; i < n_inst; ++i) {
+    st = validate_instance(h, inst[i], path, grad_p == nullptr);
+    if (st != QST_OK) return st;
+    if (!atom_grad[i]) return set_err(h, QST_ERR_INVALID_ARG, "null atom_grad entry");
+    if (grad_p && !grad_p[i]) return set_err(h, QST_ERR_INVALID_ARG, "null grad_p entry");
+    const size_t ea = path == QST_PATH_BUTTERFLY_F64 ? 16 : 8;
+    if (!aligned(atom_grad[i], ea)) return set_err(h, QST_ERR_ALIGN, "atom_grad misaligned");
+    if (atom_grad[i] == inst[i].atoms) return set_err(h, QST_ERR_INVALID_ARG, "atom_grad aliases atoms");
+    Geometry g;
+    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, elem_of(path), g);
+    if (st != QST_OK) return st;
+  }
+  st = device_gate(h);
+  if (st != QST_OK) return st;
+  for (int i = 0; i < n_inst; ++i) {
+    RunSpec rs{};
+    rs.in = &inst[i];
+    rs.path = path;
+    rs.loss_kind = loss_kind;
+    rs.eps = eps;
+    rs.grad_p = grad_p ? grad_p[i] : nullptr;
+    rs.atom_grad = atom_grad[i];
+    rs.weight_grad = weight_grad ? weight_grad[i] : nullptr;
+    rs.loss = loss ? loss + i : nullptr;
+    rs.project_tangent = project_tangent;
+    rs.adjoint = true;
+    st = run_instance(h, rs);
+    if (st != QST_OK) return st;
+  }
+  post_flag(h);
+  return QST_OK;
+}
+
+qst_status qst_reweight_simplex(qst_handle* h, const double* alpha, const double* hvec, int R, double eta_alpha,
+                                double tau, double* alpha_out, int32_t* keep_idx, int32_t* R_out) {
+  if (!h) return QST_ERR_INVALID_ARG;
+  h->last_error.clear();
+  if (!alpha || !hvec || !alpha_out || !keep_idx || !R_out) return set_err(h, QST_ERR_INVALID_ARG, "null pointer");
+  if (R < 1 || R > 1024) return set_err(h, QST_ERR_SHAPE, "R must be in 1..1024");
+  if (!std::isfinite(eta_alpha) || !std::isfinite(tau)) return set_err(h, QST_ERR_INVALID_ARG, "non-finite eta/tau");
+  if (!aligned(alpha, 8) || !aligned(hvec, 8) || !aligned(alpha_out, 8) || !aligned(keep_idx, 4) || !aligned(R_out, 4))
+    return set_err(h, QST_ERR_ALIGN, "misaligned pointer");
+  if (h->device < 0) return set_err(h, QST_ERR_UNSUPPORTED, "validation-only handle (device -1): arguments are valid");
+  if (hipSetDevice(h->device) != hipSuccess) return set_err(h, QST_ERR_DEVICE, "hipSetDevice failed");
+  QST_HIP(qst::launch_reweight(alpha, hvec, R, eta_alpha, tau, alpha_out, keep_idx, R_out, h->stream));
+  return QST_OK;
+}
+
+qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_kind, double eps, double eta_rho,
+                        double mu, double tau, int L_max, int n_lanczos, const void* v0, void* atoms_out,
+                        double* weights_out, int32_t* R_out, int32_t* s_star, double* ritz_vals, double* ritz_resid,
+                        double* q_scores, qst_path path) {
+  qst_status st = common_checks(h, inst, 1, path);
+  if (st != QST_OK) return st;
+  path = resolve(path);
+  if (path != QST_PATH_BUTTERFLY_F32 && path != QST_PATH_BUTTERFLY_F64)
+    return set_err(h, QST_ERR_UNSUPPORTED, "refactor runs on the butterfly paths");
+  if (loss_kind != QST_LOSS_CE && loss_kind != QST_LOSS_LS)
+    return set_err(h, QST_ERR_INVALID_ARG, "refactor needs a loss (CE or LS)");
+  if (!v0 || !atoms_out || !weights_out || !R_out || !s_star || !ritz_vals || !ritz_resid || !q_scores)
+    return set_err(h, QST_ERR_INVALID_ARG, "null output pointer");
+  if (L_max < 1 || L_max > 64 || n_lanczos < 1 || n_lanczos > 256)
+    return set_err(h, QST_ERR_SHAPE, "L_max must be in 1..64 and n_lanczos in 1..256");
+  if (!(eta_rho > 0.0) || !std::isfinite(eta_rho) || !std::isfinite(mu) || !std::isfinite(tau) || !(eps >= 0.0))
+    return set_err(h, QST_ERR_INVALID_ARG, "bad eta_rho/mu/tau/eps");
+  st = validate_instance(h, *inst, path, true);
+  if (st != QST_OK) return st;
+  {
+    Geometry gchk;
+    st = make_geometry(h, inst->n_qubits, inst->rank, inst->n_settings, elem_of(path), gchk);
+    if (st != QST_OK) return st;
+  }
+  st = device_gate(h);
+  if (st != QST_OK) return st;
+  const int elem = elem_of(path);
+  const bool c64 = elem == 4;
+  const int n = inst->n_qubits, R = inst->rank, B = inst->n_settings;
+  const long long D = 1ll << n;
+  Geometry gR, g1;
+  st = make_geometry(h, n, R, B, elem, gR);
+  if (st != QST_OK) return st;
+  st = make_geometry(h, n, 1, B, elem, g1);
+  if (st != QST_OK) return st;
+  const int k_max = (int)std::min<long long>(n_lanczos, D);
+  hipStream_t s = h->stream;
+
+  // Workspace: [run region for R atoms | run region for one vector | gneg | Krylov Q | w | vin | gv | A128 | misc]
+  const int SR = default_S(gR);
+  gR.S = SR;
+  const WsLayout LR = layout_ws(gR, SR, path, true, 0);
+  const int S1 = default_S(g1);
+  const WsLayout L1 = layout_ws(g1, S1, path, false, al256(LR.total));
+  size_t o = al256(L1.total);
+  const size_t off_Q = o;
+  o = al256(o + (size_t)(k_max + 1) * D * 16);
+  const size_t off_w = o;
+  o = al256(o + (size_t)D * 16);
+  const size_t off_vin = o;
+  o = al256(o + (size_t)D * 2 * elem);
+  const size_t off_gv = o;
+  o = al256(o + (size_t)D * 2 * elem);
+  const size_t off_A = o;
+  o = al256(o + (size_t)R * D * 16);
+  const size_t off_misc = o;
+  o = al256(o + 64 * 1024);
+  const size_t off_dpart = o;
+  o = al256(o + (size_t)(k_max + R + 2) * G1 * 2 * 8);
+  st = ensure_ws(h, o);
+  if (st != QST_OK) return st;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(h->ws);
+  void* gneg = ws + LR.gneg;
+  double2* Q = reinterpret_cast<double2*>(ws + off_Q);
+  double2* w = reinterpret_cast<double2*>(ws + off_w);
+  void* vin = ws + off_vin;
+  void* gv = ws + off_gv;
+  double2* A128 = reinterpret_cast<double2*>(ws + off_A);
+  double* misc = reinterpret_cast<double*>(ws + off_misc);  // [0..1]: alpha=1; [16..]: coef/dots
+  double* dpart = reinterpret_cast<double*>(ws + off_dpart);
+  double* dots = misc + 16;
+  double* coef = misc + 16 + 2 * 512;
+
+  // 1. -g of the current state (dL/dp), written by the forward pass.
+  {
+    RunSpec rs{};
+    rs.in = inst;
+    rs.path = path;
+    rs.loss_kind = loss_kind;
+    rs.eps = eps;
+    rs.gneg = gneg;
+    rs.adjoint = false;
+    rs.S_override = SR;
+    st = run_instance(h, rs, 0, nullptr);
+    if (st != QST_OK) return st;
+  }
+  // Atoms in complex128 for the low-rank term, and the unit weight of the G v products.
+  QST_HIP(qst::launch_convert(inst->atoms, c64, A128, 0, (long long)R * D, 1.0, s));
+  std::vector<double> alpha_h(R);
+  QST_HIP(hipMemcpyAsync(alpha_h.data(), inst->weights, R * sizeof(double), hipMemcpyDeviceToHost, s));
+  const double one = 1.0;
+  QST_HIP(hipMemcpyAsync(misc, &one, sizeof(double), hipMemcpyHostToDevice, s));
+
+  auto dots_host = [&](const double2* rows, int k, const void* x, int x_c64, std::vector<double>& out) -> qst_status {
+    QST_HIP(qst::launch_dots(rows, k, D, x, x_c64, D, dpart, G1, dots, s));
+    out.resize(2 * k);
+    QST_HIP(hipMemcpyAsync(out.data(), dots, 2 * k * sizeof(double), hipMemcpyDeviceToHost, s));
+    QST_HIP(hipStreamSynchronize(s));
+    return QST_OK;
+  };
+
+  // q_0 = v0 / ||v0||
+  QST_HIP(qst::launch_convert(v0, 0, Q, 0, D, 1.0, s));
+  std::vector<double> tmp;
+  st = dots_host(Q, 1, Q, 0, tmp);
+  if (st != QST_OK) return st;
+  const double nv0 = std::sqrt(tmp[0]);
+  if (!(nv0 > 0.0) || !std::isfinite(nv0)) return set_err(h, QST_ERR_INVALID_ARG, "v0 must be non-zero and finite");
+  QST_HIP(qst::launch_convert(Q, 0, Q, 0, D, 1.0 / nv0, s));
+
+  std::vector<double> a, b;
+  double scale = 0.0;
+  int k = 0;
+  for (int j = 0; j < k_max; ++j) {
+    double2* qj = Q + (size_t)j * D;
+    // low-rank term: sum_r alpha_r psi_r <psi_r, q_j>
+    st = dots_host(A128, R, qj, 0, tmp);
+    if (st != QST_OK) return st;
+    std::vector<double> cf(2 * R);
+    for (int r = 0; r < R; ++r) {
+      cf[2 * r] = alpha_h[r] * tmp[2 * r];
+      cf[2 * r + 1] = alpha_h[r] * tmp[2 * r + 1];
+    }
+    QST_HIP(hipMemcpyAsync(coef, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    QST_HIP(qst::launch_fill(w, (size_t)D * 16, s));
+    QST_HIP(qst::launch_combine(w, A128, R, D, coef, 1.0, 0, D, s));
+    // eta_rho G q_j: adjoint pass with one unit-weight atom and sensitivity -g
+    QST_HIP(qst::launch_convert(qj, 0, vin, c64, D, 1.0, s));
+    {
+      qst_instance one_inst = *inst;
+      one_inst.rank = 1;
+      one_inst.atoms = vin;
+      one_inst.weights = misc;
+      RunSpec rs{};
+      rs.in = &one_inst;
+      rs.path = path;
+      rs.loss_kind = QST_LOSS_NONE;
+      rs.grad_p = gneg;
+      rs.atom_grad = gv;
+      rs.adjoint = true;
+      rs.S_override = S1;
+      st = run_instance(h, rs, L1.pc, nullptr);
+      if (st != QST_OK) return st;
+    }
+    QST_HIP(qst::launch_axpy_c(w, 0, gv, c64, D, eta_rho, s));
+    // a_j = Re <q_j, w>
+    st = dots_host(qj, 1, w, 0, tmp);
+    if (st != QST_OK) return st;
+    const double aj = tmp[0];
+    // w -= b_{j-1} q_{j-1} + a_j q_j   (rows q_{j-1}, q_j are adjacent in Q)
+    if (j > 0) {
+      cf.assign({b[j - 1], 0.0, aj, 0.0});
+      QST_HIP(hipMemcpyAsync(coef, cf.data(), 4 * sizeof(double), hipMemcpyHostToDevice, s));
+      QST_HIP(qst::launch_combine(w, Q + (size_t)(j - 1) * D, 2, D, coef, -1.0, 0, D, s));
+    } else {
+      cf.assign({aj, 0.0});
+      QST_HIP(hipMemcpyAsync(coef, cf.data(), 2 * sizeof(double), hipMemcpyHostToDevice, s));
+      QST_HIP(qst::launch_combine(w, qj, 1, D, coef, -1.0, 0, D, s));
+    }
+    // full re-orthogonalisation, twice
+    for (int pass = 0; pass < 2; ++pass) {
+      QST_HIP(qst::launch_dots(Q, j + 1, D, w, 0, D, dpart, G1, dots, s));
+      QST_HIP(qst::launch_combine(w, Q, j + 1, D, dots, -1.0, 0, D, s));
+    }
+    st = dots_host(w, 1, w, 0, tmp);
+    if (st != QST_OK) return st;
+    const double bj = std::sqrt(std::max(tmp[0], 0.0));
+    a.push_back(aj);
+    b.push_back(bj);
+    k = j + 1;
+    scale = std::max(scale, std::max(std::fabs(aj), bj));
+    if (j + 1 == k_max || bj <= 1e-13 * std::max(scale, 1e-300)) break;
+    QST_HIP(qst::launch_convert(w, 0, Q + (size_t)(j + 1) * D, 0, D, 1.0 / bj, s));
+  }
+
+  // Tridiagonal eigenproblem on the host (FP64).
+  std::vector<double> T((size_t)k * k, 0.0), ev, Y;
+  for (int i = 0; i < k; ++i) {
+    T[(size_t)i * k + i] = a[i];
+    if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = b[i];
+  }
+  jacobi_eigh(T, k, ev, Y);
+  std::vector<int> order(k);
+  for (int i = 0; i < k; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ev[x] > ev[y]; });
+  const int L = std::min(L_max, k);
+  std::vector<double> theta(L), resid(L);
+  for (int l = 0; l < L; ++l) {
+    theta[l] = ev[order[l]];
+    resid[l] = std::fabs(b[k - 1] * Y[(size_t)(k - 1) * k + order[l]]);
+  }
+  // Candidates s = 1..L: beta = proj(theta_1..s), prune, score.
+  std::vector<double> scores(L);
+  std::vector<std::vector<int>> keeps(L);
+  std::vector<std::vector<double>> wts(L);
+  for (int sidx = 0; sidx < L; ++sidx) {
+    std::vector<double> lam(theta.begin(), theta.begin() + sidx + 1);
+    std::vector<double> beta = proj_simplex(lam);
+    std::vector<int> keep;
+    double sum = 0.0;
+    for (int i = 0; i <= sidx; ++i)
+      if (beta[i] > tau) {
+        keep.push_back(i);
+        sum += beta[i];
+      }
+    if (keep.empty()) {
+      int arg = 0;
+      for (int i = 1; i <= sidx; ++i)
+        if (beta[i] > beta[arg]) arg = i;
+      keep.push_back(arg);
+      sum = beta[arg];
+    }
+    std::vector<double> bc;
+    double sq = 0.0, lin = 0.0;
+    for (int i : keep) {
+      bc.push_back(beta[i] / sum);
+      sq += (beta[i] / sum) * (beta[i] / sum);
+      lin += (beta[i] / sum) * theta[i];
+    }
+    scores[sidx] = (sq - 2.0 * lin) / (2.0 * eta_rho) + mu * (double)keep.size();
+    keeps[sidx] = keep;
+    wts[sidx] = bc;
+  }
+  int best = 0;
+  for (int i = 1; i < L; ++i)
+    if (scores[i] < scores[best]) best = i;
+  const std::vector<int>& keep = keeps[best];
+  const int Rout = (int)keep.size();
+
+  // Ritz vectors of the chosen candidate: phi_l = sum_j Y[j][l] q_j, written to atoms_out.
+  QST_HIP(qst::launch_fill(atoms_out, (size_t)L_max * D * 2 * elem, s));
+  for (int i = 0; i < Rout; ++i) {
+    std::vector<double> cf(2 * k, 0.0);
+    for (int j = 0; j < k; ++j) cf[2 * j] = Y[(size_t)j * k + order[keep[i]]];
+    QST_HIP(hipMemcpyAsync(coef, cf.data(), cf.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    QST_HIP(qst::launch_fill(w, (size_t)D * 16, s));
+    QST_HIP(qst::launch_combine(w, Q, k, D, coef, 1.0, 0, D, s));
+    QST_HIP(qst::launch_convert(w, 0, reinterpret_cast<unsigned char*>(atoms_out) + (size_t)i * D * 2 * elem, c64, D,
+                                1.0, s));
+    QST_HIP(hipStreamSynchronize(s));  // coef is reused by the next row
+  }
+  std::vector<double> wout(L_max, 0.0), rv(L_max, 0.0), rr(L_max, 0.0), qs(L_max, 0.0);
+  for (int i = 0; i < Rout; ++i) wout[i] = wts[best][i];
+  for (int l = 0; l < L; ++l) {
+    rv[l] = theta[l];
+    rr[l] = resid[l];
+    qs[l] = scores[l];
+  }
+  const int32_t ro = Rout, sb = best;
+  QST_HIP(hipMemcpyAsync(weights_out, wout.data(), L_max * sizeof(double), hipMemcpyHostToDevice, s));
+  QST_HIP(hipMemcpyAsync(ritz_vals, rv.data(), L_max * sizeof(double), hipMemcpyHostToDevice, s));
+  QST_HIP(hipMemcpyAsync(ritz_resid, rr.data(), L_max * sizeof(double), hipMemcpyHostToDevice, s));
+  QST_HIP(hipMemcpyAsync(q_scores, qs.data(), L_max * sizeof(double), hipMemcpyHostToDevice, s));
+  QST_HIP(hipMemcpyAsync(R_out, &ro, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  QST_HIP(hipMemcpyAsync(s_star, &sb, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  QST_HIP(hipStreamSynchronize(s));
+  post_flag(h);
+  return QST_OK;
+}
+
+}  // extern "C"

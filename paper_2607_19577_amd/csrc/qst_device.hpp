@@ -1,0 +1,260 @@
+// Device helpers shared by the butterfly kernels: complex types, the unscaled
+// single-qubit Pauli rotations, in-register butterflies, layouts and the
+// padded LDS indexing used by the transposes.
+//
+// A "block" is a power-of-two set of amplitudes a work-group holds on chip.
+// Each thread keeps V = 2^LOGV of them in registers.  A *layout* is named by
+// `lo`: the thread's in-register index i supplies block bits [lo, lo+LOGV)
+// and the thread index supplies the remaining bits in increasing order, so
+// consecutive threads touch consecutive addresses whenever lo > 0 (coalesced
+// global access).  A qubit whose bit lies in [lo, lo+LOGV) is a butterfly
+// between two registers of one thread; moving between layouts is a transpose
+// through LDS.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qst {
+
+template <typename T> struct cx_of;
+template <> struct cx_of<float> { using type = float2; };
+template <> struct cx_of<double> { using type = double2; };
+template <typename T> using cx = typename cx_of<T>::type;
+
+// Pauli codes as stored in a setting: X = 0, Y = 1, Z = 2.  Codes 2 and 3 mean
+// "no rotation" inside the 2-bit code words handed to xform().
+constexpr uint32_t CODE_SKIP = 2u;
+
+// LDS index with one pad slot every 32 elements: a stride-32 access pattern
+// (in-register bits at the bottom of the block) then spreads over all banks.
+__device__ __forceinline__ int pad32(int p) { return p + (p >> 5); }
+
+// Block position of register i of thread tau in the layout `lo`.
+template <int LOGV>
+__device__ __forceinline__ int lay_pos(int tau, int i, int lo) {
+  const int m = (1 << lo) - 1;
+  return ((tau & ~m) << LOGV) | (i << lo) | (tau & m);
+}
+
+// pad32(lay_pos(tau, i, lo)) split into a per-thread base and a per-register
+// constant: with p = H | (i << lo) | L (H a multiple of 2^(lo+LOGV), L < 2^lo),
+// p >> 5 = H >> 5 + (lo >= 5 ? (i << (lo-5)) + (L >> 5) : i >> (5-lo)), so
+// the register part becomes an immediate LDS offset.
+template <int LOGV, int LO>
+__device__ __forceinline__ int pad_base(int tau) {
+  constexpr int m = (1 << LO) - 1;
+  const int H = (tau & ~m) << LOGV;
+  const int L = tau & m;
+  return H + L + (H >> 5) + (LO >= 5 ? (L >> 5) : 0);
+}
+template <int LO>
+__host__ __device__ constexpr int pad_off(int i) {
+  return (i << LO) + (LO >= 5 ? (i << (LO - 5)) : (i >> (5 - LO)));
+}
+
+// Unscaled rotations: sqrt2 * V_X = [[1,1],[1,-1]], sqrt2 * V_Y = [[1,-i],[1,i]]
+// (rows <+| and <-|, resp. <+i| and <-i|); the pair is (a, b) = (bit 0, bit 1).
+// The 1/sqrt2 factors are applied once per setting as the exact power of two
+// 2^(-k_b) on |phi|^2.
+//
+// Each butterfly updates its pair in place: b' is formed first and a' is then
+// recovered as 2a - b' with one fused multiply-add (a' = a + s, b' = a - s).
+// The extra rounding is one ulp of |(a, b)|, well inside the FP32 tolerance,
+// and the form needs no temporaries beyond the pair itself.  Amplitudes are
+// kept as separate real and imaginary register arrays: with the code of each
+// bit known only at run time, the (X, Y, skip) branches then merge without
+// re-pairing registers.
+template <typename T>
+__device__ __forceinline__ void bf_x(T& ax, T& ay, T& bx, T& by) {
+  bx = ax - bx;
+  by = ay - by;
+  ax = fma(T(2), ax, -bx);
+  ay = fma(T(2), ay, -by);
+}
+// a' = a - i b, b' = a + i b
+template <typename T>
+__device__ __forceinline__ void bf_y(T& ax, T& ay, T& bx, T& by) {
+  const T nbx = ax - by;
+  by = ay + bx;
+  bx = nbx;
+  ax = fma(T(2), ax, -bx);
+  ay = fma(T(2), ay, -by);
+}
+// Adjoint of the Y rotation, [[1,1],[i,-i]]: a' = a + b, b' = i (a - b)
+template <typename T>
+__device__ __forceinline__ void bf_yh(T& ax, T& ay, T& bx, T& by) {
+  const T nbx = by - ay;
+  by = ax - bx;
+  bx = nbx;
+  ax = fma(T(2), ax, -by);
+  ay = fma(T(2), ay, bx);
+}
+// Complex-pair forms (used by the single-pass reference kernels).
+template <typename C2> __device__ __forceinline__ void bf_x(C2& a, C2& b) { bf_x(a.x, a.y, b.x, b.y); }
+template <typename C2> __device__ __forceinline__ void bf_y(C2& a, C2& b) { bf_y(a.x, a.y, b.x, b.y); }
+template <typename C2> __device__ __forceinline__ void bf_yh(C2& a, C2& b) { bf_yh(a.x, a.y, b.x, b.y); }
+
+template <int K, int LOGV, int CODE, bool ADJ, typename T>
+__device__ __forceinline__ void pairs(T (&x)[1 << LOGV], T (&y)[1 << LOGV]) {
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) {
+    if (i & (1 << K)) continue;
+    const int j = i | (1 << K);
+    if (CODE == 0) {
+      bf_x(x[i], y[i], x[j], y[j]);
+    } else if (ADJ) {
+      bf_yh(x[i], y[i], x[j], y[j]);
+    } else {
+      bf_y(x[i], y[i], x[j], y[j]);
+    }
+  }
+}
+
+template <int K, int LOGV, bool ADJ, typename T>
+__device__ __forceinline__ void xform_bit(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
+  if constexpr (K < LOGV) {
+    const uint32_t c = (codes >> (2 * K)) & 3u;
+    if (c == 0u) {
+      pairs<K, LOGV, 0, ADJ>(x, y);
+    } else if (c == 1u) {
+      pairs<K, LOGV, 1, ADJ>(x, y);
+    }
+    xform_bit<K + 1, LOGV, ADJ>(x, y, codes);
+  }
+}
+
+// Apply the rotations of the in-register bits; `codes` holds 2 bits per
+// register bit (must be uniform across the work-group).
+template <int LOGV, bool ADJ, typename T>
+__device__ __forceinline__ void xform(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
+  xform_bit<0, LOGV, ADJ>(x, y, codes);
+}
+
+// Branch-free variant for code paths that must not branch per bit.  A row
+// phase on V_b changes neither |V_b psi|^2 nor V_b^dagger (g * V_b psi), so a
+// Z bit may be applied as diag(1,-1) instead of the identity, provided the
+// adjoint pass does the same (diag(1,-1) is its own adjoint).  Then every
+// active bit takes one of three in-register forms selected by uniform
+// coefficients f = [code != Z] and y = [code == Y]:
+//   forward:  s = y ? -i b : b;   a' = a + f s;   b' = f a - s
+//   adjoint:  t = f a - b;        a' = a + f b;   b' = y ? i t : t
+// which give (a+b, a-b) for X, (a-ib, a+ib) resp. (a+b, i(a-b)) for Y and
+// (a, -b) for Z.  Bits outside ACTIVE (not qubits of this pass) are untouched.
+template <int K, int LOGV, bool ADJ, typename T>
+__device__ __forceinline__ void bit_uniform(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t c) {
+  const T f = c < 2u ? T(1) : T(0);
+  const bool isy = c == 1u;
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) {
+    if (i & (1 << K)) continue;
+    const int j = i | (1 << K);
+    if (!ADJ) {
+      const T sx = isy ? y[j] : x[j];
+      const T sy = isy ? -x[j] : y[j];
+      const T nbx = fma(f, x[i], -sx);
+      const T nby = fma(f, y[i], -sy);
+      x[i] = fma(f, sx, x[i]);
+      y[i] = fma(f, sy, y[i]);
+      x[j] = nbx;
+      y[j] = nby;
+    } else {
+      const T tx = fma(f, x[i], -x[j]);
+      const T ty = fma(f, y[i], -y[j]);
+      x[i] = fma(f, x[j], x[i]);
+      y[i] = fma(f, y[j], y[i]);
+      x[j] = isy ? -ty : tx;
+      y[j] = isy ? tx : ty;
+    }
+  }
+}
+
+template <int K, int LOGV, bool ADJ, uint32_t ACTIVE, typename T>
+__device__ __forceinline__ void xform_uniform_bit(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
+  if constexpr (K < LOGV) {
+    if constexpr ((ACTIVE >> K) & 1u) bit_uniform<K, LOGV, ADJ>(x, y, (codes >> (2 * K)) & 3u);
+    xform_uniform_bit<K + 1, LOGV, ADJ, ACTIVE>(x, y, codes);
+  }
+}
+
+template <int LOGV, bool ADJ, uint32_t ACTIVE, typename T>
+__device__ __forceinline__ void xform_uniform(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
+  xform_uniform_bit<0, LOGV, ADJ, ACTIVE>(x, y, codes);
+}
+
+// Code word of the layout `lo` for the bits [from, to) of the block, where
+// block bit q is index bit gbit0 + (q - qbase) of the state (q >= qbase).
+// Bits outside [from, to) are skipped.
+template <int LOGV>
+__device__ __forceinline__ uint32_t layout_codes(uint64_t pc, int lo, int from, int to, int qbase, int gbit0) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < LOGV; ++k) {
+    const int q = lo + k;
+    uint32_t ck = CODE_SKIP;
+    if (q >= from && q < to) ck = (uint32_t)((pc >> (2 * (gbit0 + q - qbase))) & 3ull);
+    c |= ck << (2 * k);
+  }
+  return __builtin_amdgcn_readfirstlane(c);
+}
+
+// Number of non-Z qubits of a decoded setting (codes were clamped to <= 2).
+__device__ __forceinline__ int nonz_count(uint64_t pc, int n) {
+  const uint64_t odd = 0x5555555555555555ull;
+  const uint64_t zbits = (pc >> 1) & odd;  // 1 where the code is 2 (Z)
+  return n - __popcll(zbits);
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// ---------------------------------------------------------------- buffer access
+// Global traffic of the staged kernels goes through raw buffer instructions:
+// one resource (uniform base, byte size as bound) per array, one VGPR byte
+// offset per thread shared by all of a thread's elements, and the per-element
+// part as a uniform SGPR offset.  Out-of-range offsets read zero and drop
+// writes, so a wrong index cannot reach memory outside the array.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int RSRC_WORD3 = 0x00020000;  // gfx9-family raw buffer descriptor word 3
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, RSRC_WORD3);
+}
+
+using u32x2 = __attribute__((ext_vector_type(2))) unsigned int;
+using u32x4 = __attribute__((ext_vector_type(4))) unsigned int;
+
+__device__ __forceinline__ void bload(float2& v, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bload(double2& v, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(const float2& v, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(const double2& v, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs, (int)voff, (int)soff, 0);
+}
+
+// Layout chain of a block of 2^NB amplitudes with 2^LOGV registers per thread:
+// lo(0) = NB - LOGV, then LOGV bits lower per step down to 0.
+template <int NB, int LOGV>
+struct Chain {
+  static constexpr int lo(int k) {
+    int l = NB - LOGV;
+    for (int j = 0; j < k; ++j) l = l - LOGV > 0 ? l - LOGV : 0;
+    return l;
+  }
+  static constexpr int count() {
+    int k = 1;
+    while (lo(k - 1) > 0) ++k;
+    return k;
+  }
+  // first block bit handled by layout k (bits [lo(k), top(k)) are new there)
+  static constexpr int top(int k) { return k == 0 ? NB : lo(k - 1); }
+};
+
+}  // namespace qst

@@ -1,0 +1,93 @@
+// Internal interfaces between the host API and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qst {
+
+// Geometry of one instance on the staged butterfly path.
+//   n_lo : low qubits (index bits [0, n_lo)), handled by the fused stage with all
+//          atoms on chip; R * 2^n_lo fits one work-group's LDS.
+//   n_hi : high qubits (bits [n_lo, n)), handled by the tile stages A and C.
+//   t, c : the tile stages hold 2^t amplitudes of one atom: 2^n_hi rows (stride
+//          2^n_lo) by 2^c contiguous columns, t = n_hi + c.
+//   cpw  : low-stage chunks (of 2^n_lo amplitudes) per work-group.
+//   S    : settings per batch (X and W hold S x R x D amplitudes).
+struct Geometry {
+  int n, R, B;
+  long long D;
+  int n_lo, n_hi, t, c;
+  int logv_lo;  // registers per thread in the low stage: 2^logv_lo
+  int cpw;
+  int S;
+  int elem;      // bytes per real (4 or 8)
+  long long items_per_setting;  // low-stage work-groups per setting = 2^n_hi / cpw
+};
+
+struct LoArgs {
+  const void* src;            // X [S][R][D] or the atoms [R][D]
+  long long src_set_stride;   // elements between consecutive settings in src (0: atoms)
+  void* dst;                  // W [S][R][D] (adjoint pass)
+  const uint64_t* pc;         // decoded settings [B]
+  const double* alpha;        // [R]
+  const float* freqs;         // [B][D] or null
+  const void* grad_p;         // [B][D] or null (generic sensitivity)
+  void* probs;                // [B][D] or null
+  void* gneg;                 // [B][D] or null: receives -dL/dp
+  double* part;               // [(R+1)][nslots]: row 0 loss, rows 1..R weight gradient
+  long long nslots;
+  long long D;
+  int R, n, n_lo, n_hi, log_ta, cpw, b0, B;
+  int loss_kind;
+  double eps;
+};
+
+struct HiArgs {
+  const void* src;  // forward: atoms [R][D];   adjoint: W [S][R][D]
+  void* dst;        // forward: X [S][R][D];    adjoint: atom gradient [R][D]
+  const uint64_t* pc;
+  long long D;
+  int R, n, n_lo, n_hi, t, c, b0, S, first;
+};
+
+// Launchers (return the HIP status of the launch).
+hipError_t launch_decode(const uint8_t* settings, int B, int N, uint64_t* pc, int* flag, hipStream_t st);
+hipError_t launch_stage_lo(const Geometry& g, const LoArgs& a, int S, bool adjoint, hipStream_t st);
+hipError_t launch_stage_hi(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st);
+hipError_t launch_sum_settings(const Geometry& g, const void* W, int S, void* grad, int first, hipStream_t st);
+hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
+// part [rows][nslots] -> out[rows] (two-level, fixed order).  out_stride: spacing of out entries.
+hipError_t launch_rowsum(const double* part, int rows, long long nslots, double* lvl1, int g1, double* out,
+                         hipStream_t st);
+// Write the reduced loss / weight gradient to the caller's buffers.
+hipError_t launch_scatter_results(const double* sums, int R, double* loss, double* wgrad, hipStream_t st);
+// a7: grad[r] -= psi_r <psi_r, grad[r]>  (per atom, FP64 inner products)
+hipError_t launch_tangent(int elem, const void* atoms, void* grad, int R, long long D, double* scratch,
+                          int g1, hipStream_t st);
+hipError_t launch_reweight(const double* alpha, const double* h, int R, double eta, double tau,
+                           double* alpha_out, int32_t* keep, int32_t* R_out, hipStream_t st);
+
+// Plain per-qubit reference path (FP32).
+hipError_t launch_plain_copy(const void* atoms, void* X, int S, int R, long long D, hipStream_t st);
+hipError_t launch_plain_qubit(void* X, int S, int R, long long D, int bit, const uint64_t* pc, int b0, bool adj,
+                              hipStream_t st);
+hipError_t launch_plain_point(const LoArgs& a, void* X, int S, hipStream_t st);
+hipError_t launch_plain_sum(const void* X, int S, int R, long long D, void* grad, int first, hipStream_t st);
+
+// Vector helpers for the refactorisation (complex128 Krylov vectors).
+hipError_t launch_dots(const void* Q, int k, long long ldq, const void* w, int w_is_c64, long long D,
+                       double* part, int g1, double* out_re_im, hipStream_t st);
+hipError_t launch_combine(void* w, const void* Q, int k, long long ldq, const double* coef_re_im, double sign,
+                          int q_is_c64, long long D, hipStream_t st);
+hipError_t launch_convert(const void* src, int src_c64, void* dst, int dst_c64, long long n, double scale_re,
+                          hipStream_t st);
+hipError_t launch_axpy_c(void* y, int y_c64, const void* x, int x_c64, long long n, double a, hipStream_t st);
+
+// MFMA tile path (fused 4-qubit 16x16 Kronecker tiles).
+hipError_t launch_tile_lo(const Geometry& g, const LoArgs& a, int S, bool adjoint, bool bf16, hipStream_t st);
+hipError_t launch_tile_hi(const Geometry& g, const HiArgs& a, bool adjoint, bool bf16, hipStream_t st);
+
+size_t lo_lds_bytes(const Geometry& g);
+size_t hi_lds_bytes(const Geometry& g);
+
+}  // namespace qst

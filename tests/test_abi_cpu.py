@@ -1,0 +1,115 @@
+"""The C-ABI library loads on a CPU host, exports every entry point that
+include/qst.h declares, and its argument validation behaves as documented
+(validation-only handle: nothing is launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2607_19577_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "qst.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qst_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libqst.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_exports_match_header(lib):
+    declared = _declared()
+    assert set(declared) == set(_lib.EXPORTS), declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_static_strings(lib):
+    assert lib.qst_status_string(0) == b"ok"
+    assert b"gfx950" in lib.qst_build_info()
+    for s in range(9):
+        assert lib.qst_status_string(s)
+
+
+def _vh(lib):
+    h = ctypes.c_void_p()
+    assert lib.qst_create(-1, None, ctypes.byref(h)) == 0
+    return h
+
+
+def _inst(n=10, R=4, B=3, atoms=0x1000, weights=0x2000, settings=0x3000, freqs=0x4000):
+    return _lib.QstInstance(n, R, B, 0, atoms, weights, settings, freqs)
+
+
+def test_validation_paths(lib):
+    h = _vh(lib)
+    try:
+        one = (_lib.QstInstance * 1)(_inst())
+        ok_args = dict(loss=_lib.LOSS_CE, eps=1e-8, path=_lib.PATH_AUTO)
+        # valid arguments on a validation-only handle stop before any launch
+        assert lib.qst_forward(h, one, 1, None, ctypes.c_void_p(0x5000), _lib.LOSS_CE, 1e-8, 0) == 4
+        # shape errors
+        for bad in (_inst(n=0), _inst(n=21), _inst(R=0), _inst(R=17), _inst(B=0)):
+            arr = (_lib.QstInstance * 1)(bad)
+            assert lib.qst_forward(h, arr, 1, None, None, _lib.LOSS_NONE, 0.0, 0) == 2
+        # null pointers
+        for bad in (_inst(atoms=0), _inst(weights=0), _inst(settings=0)):
+            arr = (_lib.QstInstance * 1)(bad)
+            assert lib.qst_forward(h, arr, 1, None, None, _lib.LOSS_NONE, 0.0, 0) == 1
+        assert lib.qst_forward(h, one, 0, None, None, 2, 0.0, 0) == 1
+        assert lib.qst_forward(None, one, 1, None, None, 2, 0.0, 0) == 1
+        # loss without freqs, bad enums, bad eps
+        arr = (_lib.QstInstance * 1)(_inst(freqs=0))
+        assert lib.qst_forward(h, arr, 1, None, ctypes.c_void_p(0x5000), _lib.LOSS_CE, 1e-8, 0) == 1
+        assert lib.qst_forward(h, one, 1, None, None, 7, 1e-8, 0) == 1
+        assert lib.qst_forward(h, one, 1, None, None, 0, -1.0, 0) == 1
+        assert lib.qst_forward(h, one, 1, None, None, 0, float("nan"), 0) == 1
+        assert lib.qst_forward(h, one, 1, None, None, 0, 1e-8, 99) == 1
+        # misaligned atoms
+        arr = (_lib.QstInstance * 1)(_inst(atoms=0x1004))
+        assert lib.qst_forward(h, arr, 1, None, None, 2, 0.0, 0) == 3
+        # backward: needs atom_grad, exclusive grad_p / loss
+        grads = (ctypes.c_void_p * 1)(0x6000)
+        gp = (ctypes.c_void_p * 1)(0x7000)
+        assert lib.qst_backward(h, one, 1, None, None, None, None, 0, 1e-8, 0, 0) == 1
+        assert lib.qst_backward(h, one, 1, gp, grads, None, None, _lib.LOSS_CE, 1e-8, 0, 0) == 1
+        assert lib.qst_backward(h, one, 1, None, grads, None, None, _lib.LOSS_NONE, 1e-8, 0, 0) == 1
+        assert lib.qst_backward(h, one, 1, gp, grads, None, None, _lib.LOSS_NONE, 0.0, 0, 0) == 4
+        alias = (ctypes.c_void_p * 1)(0x1000)
+        assert lib.qst_backward(h, one, 1, None, alias, None, None, 0, 1e-8, 0, 0) == 1
+        # FP64 path: whole state on chip only
+        big = (_lib.QstInstance * 1)(_inst(n=14, R=4, atoms=0x10000))
+        assert lib.qst_forward(h, big, 1, None, None, 2, 0.0, _lib.PATH_BUTTERFLY_F64) == 4
+        assert b"FP64" in lib.qst_last_error(h)
+        # reweight
+        assert lib.qst_reweight_simplex(h, None, None, 4, 0.1, 1e-3, None, None, None) == 1
+        p = ctypes.c_void_p(0x8000)
+        assert lib.qst_reweight_simplex(h, p, p, 0, 0.1, 1e-3, p, p, p) == 2
+        assert lib.qst_reweight_simplex(h, p, p, 2000, 0.1, 1e-3, p, p, p) == 2
+        assert lib.qst_reweight_simplex(h, p, p, 8, float("inf"), 1e-3, p, p, p) == 1
+        assert lib.qst_reweight_simplex(h, p, p, 8, 0.1, 1e-3, p, p, p) == 4
+        # refactor
+        v = ctypes.c_void_p(0x9000)
+        assert lib.qst_refactor(h, one, _lib.LOSS_NONE, 1e-8, 0.5, 1e-3, 1e-3, 8, 30, v, v, v, v, v, v, v, v, 0) == 1
+        assert lib.qst_refactor(h, one, _lib.LOSS_CE, 1e-8, 0.0, 1e-3, 1e-3, 8, 30, v, v, v, v, v, v, v, v, 0) == 1
+        assert lib.qst_refactor(h, one, _lib.LOSS_CE, 1e-8, 0.5, 1e-3, 1e-3, 0, 30, v, v, v, v, v, v, v, v, 0) == 2
+        assert lib.qst_refactor(h, one, _lib.LOSS_CE, 1e-8, 0.5, 1e-3, 1e-3, 8, 30, v, v, v, v, v, v, v, v, 0) == 4
+        assert ok_args
+    finally:
+        assert lib.qst_destroy(h) == 0
+
+
+def test_create_without_device(lib):
+    # On a host without a GPU (or with a bad index) creation fails cleanly.
+    h = ctypes.c_void_p()
+    rc = lib.qst_create(4096, None, ctypes.byref(h))
+    assert rc in (1, 5) and not h.value
+    assert lib.qst_destroy(None) == 1

@@ -1,0 +1,244 @@
+"""GPU parity of the C-ABI hot path against the FP64 oracle.
+
+Tolerances: norm-wise relative error (plus an element-wise bound scaled by the
+largest reference element) <= 1e-5 for the FP32 butterfly path, <= 1e-12 for
+the FP64 path.  Shapes cover the single-pass geometry (whole state on chip),
+the two-pass geometry with one and two tile layouts, ragged setting batches,
+and the full n=20, R=16, B=2000 workload on sampled settings and closed forms.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import born, pauli
+from tests._cases import close, make_case, oracle, rel, to_device
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+TOL32, TOL64 = 1e-5, 1e-12
+
+
+@pytest.fixture(scope="module")
+def h():
+    from paper_2607_19577_amd import api
+
+    with api.Handle(0) as hd:
+        yield hd
+
+
+def _run(h, case, kind, path, eps=1e-8, grad_p=None):
+    from paper_2607_19577_amd import api
+
+    inst = to_device(case, DEV)
+    probs, _ = api.qst_forward(h, [inst], want_probs=True, path=path)
+    if grad_p is None:
+        lt, ag, wg = api.qst_backward(h, [inst], loss=kind, eps=eps, path=path)
+        loss = float(lt[0])
+    else:
+        _, ag, wg = api.qst_backward(h, [inst], grad_p=[torch.from_numpy(grad_p).to(DEV)], path=path)
+        loss = None
+    torch.cuda.synchronize()
+    return loss, probs[0].cpu().numpy(), ag[0].cpu().numpy(), wg[0].cpu().numpy()
+
+
+def _check(got, ref, tol, what=""):
+    L, p, ga, gw = got
+    Lr, pr, gar, gwr = ref
+    if Lr is not None:
+        assert abs(L - Lr) <= tol * abs(Lr), (what, "loss", L, Lr)
+    assert close(p, pr, tol), (what, "probs", rel(p, pr))
+    for r in range(ga.shape[0]):
+        assert close(ga[r], gar[r], tol), (what, "atom_grad", r, rel(ga[r], gar[r]))
+    assert close(gw, gwr, tol), (what, "weight_grad", rel(gw, gwr))
+
+
+def test_cfg1_all_paulis_fp64_ls(h):
+    """n=4, R=2, all 81 Pauli strings, complex128, LS loss: FP64 path vs the dense-POVM oracle."""
+    from paper_2607_19577_amd import api
+
+    case = make_case(101, 4, 2, 81, shots=1000, complex_dtype=np.complex128, exhaustive=True)
+    ref = oracle(case, born.LOSS_LS, 0.0, tier="dense")
+    _check(_run(h, case, api.LOSS_LS, api.PATH_BUTTERFLY_F64, eps=0.0), ref, TOL64, "cfg1 f64")
+    ref_ce = oracle(case, born.LOSS_CE, 1e-8, tier="dense")
+    _check(_run(h, case, api.LOSS_CE, api.PATH_BUTTERFLY_F64), ref_ce, TOL64, "cfg1 f64 ce")
+    case32 = dict(case, atoms=case["atoms"].astype(np.complex64))
+    ref32 = oracle(case32, born.LOSS_LS, 0.0, tier="dense")
+    _check(_run(h, case32, api.LOSS_LS, api.PATH_BUTTERFLY_F32, eps=0.0), ref32, TOL32, "cfg1 f32")
+
+
+@pytest.mark.parametrize("kind", [born.LOSS_CE, born.LOSS_LS])
+def test_cfg2_n10_r4_b200(h, kind):
+    from paper_2607_19577_amd import api
+
+    case = make_case(102, 10, 4, 200, shots=10_000)
+    ref = oracle(case, kind, 1e-8, tier="axis")
+    _check(_run(h, case, kind, api.PATH_BUTTERFLY_F32), ref, TOL32, f"cfg2 kind={kind}")
+
+
+@pytest.mark.parametrize("n,R,B", [
+    (1, 1, 3), (3, 2, 5), (5, 7, 4), (7, 3, 9), (9, 16, 6),   # single pass, few registers per thread
+    (12, 5, 37),                                          # two passes, tile 2^12 x 1 high bit
+    (13, 9, 19),                                          # tile 2^13, 3 high bits
+    (14, 1, 7),                                           # low stage with three layouts
+    (15, 16, 11),                                         # tile 2^14, 5 high bits (one layout)
+    (16, 16, 5),                                          # 6 high bits: two tile layouts
+    (17, 3, 3),                                           # n_lo = 12, 5 high bits
+])
+def test_shapes_fp32(h, n, R, B):
+    from paper_2607_19577_amd import api
+
+    case = make_case(200 + n * 31 + R, n, R, B, shots=5000)
+    ref = oracle(case, born.LOSS_CE, 1e-8, tier="axis")
+    _check(_run(h, case, api.LOSS_CE, api.PATH_BUTTERFLY_F32), ref, TOL32, f"n={n} R={R} B={B}")
+
+
+@pytest.mark.parametrize("n,R,B", [(2, 1, 9), (6, 3, 8), (8, 5, 7), (11, 4, 5)])
+def test_shapes_fp64(h, n, R, B):
+    from paper_2607_19577_amd import api
+
+    case = make_case(300 + n, n, R, B, shots=5000, complex_dtype=np.complex128)
+    ref = oracle(case, born.LOSS_CE, 1e-8, tier="axis")
+    _check(_run(h, case, api.LOSS_CE, api.PATH_BUTTERFLY_F64), ref, TOL64, f"f64 n={n} R={R} B={B}")
+
+
+def test_generic_sensitivity_and_tangent(h):
+    """grad_p mode (autograd route) and the tangent-space projection."""
+    from paper_2607_19577_amd import api
+
+    case = make_case(401, 13, 6, 10, shots=5000)
+    rng = synth.make_rng(5)
+    gp = rng.standard_normal((10, 1 << 13)).astype(np.float32)
+    ref = oracle(case, tier="axis", grad_p=gp.astype(np.float64))
+    _check(_run(h, case, None, api.PATH_BUTTERFLY_F32, grad_p=gp), ref, TOL32, "grad_p")
+    inst = to_device(case, DEV)
+    _, ag, _ = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, project_tangent=True)
+    _, _, ga_ref, _ = oracle(case, born.LOSS_CE, 1e-8)
+    t_ref = born.tangent_project(case["atoms"].astype(np.complex128), ga_ref)
+    got = ag[0].cpu().numpy()
+    for r in range(6):
+        assert close(got[r], t_ref[r], TOL32), rel(got[r], t_ref[r])
+
+
+def test_batched_instances_match_single(h):
+    """Several instances of different shapes in one call equal one-at-a-time calls bit for bit."""
+    from paper_2607_19577_amd import api
+
+    cases = [make_case(500 + i, n, R, B, shots=2000) for i, (n, R, B) in enumerate([(8, 3, 20), (12, 5, 9), (6, 1, 50)])]
+    insts = [to_device(c, DEV) for c in cases]
+    lt, ag, wg = api.qst_backward(h, insts, loss=api.LOSS_CE, eps=1e-8)
+    for i, inst in enumerate(insts):
+        l1, a1, w1 = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8)
+        assert torch.equal(lt[i:i + 1], l1) and torch.equal(ag[i], a1[0]) and torch.equal(wg[i], w1[0])
+
+
+def test_deterministic(h):
+    from paper_2607_19577_amd import api
+
+    case = make_case(601, 16, 16, 9, shots=2000)
+    inst = to_device(case, DEV)
+    a = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8)
+    b = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1][0], b[1][0]) and torch.equal(a[2][0], b[2][0])
+
+
+def test_bad_code_flag(h):
+    """A Pauli code > 2 in device memory is treated as Z and reported by a later call."""
+    from paper_2607_19577_amd import api
+
+    case = make_case(602, 6, 2, 4, shots=100)
+    case["settings"][1, 2] = 7
+    inst = to_device(case, DEV)
+    api.qst_forward(h, [inst], want_probs=True)
+    torch.cuda.synchronize()
+    with pytest.raises(api.QSTError) as ei:
+        api.qst_forward(h, [inst], want_probs=True)
+    assert ei.value.status == 7
+    torch.cuda.synchronize()
+    ok = make_case(603, 6, 2, 4, shots=100)
+    api.qst_forward(h, [to_device(ok, DEV)], want_probs=True)
+
+
+# ---------------------------------------------------------------- full workload n=20, R=16, B=2000
+@pytest.fixture(scope="module")
+def big():
+    rng = synth.make_rng(7001)
+    n, R, B = 20, 16, 2000
+    atoms = synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64)
+    w = synth.dirichlet_weights(rng, R)
+    s = synth.random_settings(rng, B, n)
+    freqs = synth.porter_thomas_freqs_torch(7002, B, 1 << n, synth.dirichlet_weights(rng, 4), 1_000_000, DEV)
+    return dict(atoms=atoms, weights=w, settings=s, freqs_dev=freqs)
+
+
+def _big_inst(big):
+    from paper_2607_19577_amd import api
+
+    return api.Instance(torch.from_numpy(big["atoms"]).to(DEV), torch.from_numpy(big["weights"]).to(DEV),
+                        torch.from_numpy(big["settings"]).to(DEV), big["freqs_dev"])
+
+
+def test_full_size_sampled_probabilities(h, big):
+    from paper_2607_19577_amd import api
+
+    inst = _big_inst(big)
+    probs, lt = api.qst_forward(h, [inst], want_probs=True, loss=api.LOSS_CE)
+    torch.cuda.synchronize()
+    p = probs[0]
+    rows = [0, 777, 1999]
+    ref = born.probs_axis(big["atoms"].astype(np.complex128), big["weights"], big["settings"], rows=rows)
+    got = p[rows].cpu().numpy()
+    for i in range(len(rows)):
+        assert close(got[i], ref[i], TOL32), (rows[i], rel(got[i], ref[i]))
+    # Every setting's probabilities sum to sum_r alpha_r ||psi_r||^2 (= 1 up to the FP32 atoms' norms).
+    norms = (np.abs(big["atoms"].astype(np.complex128)) ** 2).sum(axis=1)
+    target = float(np.dot(big["weights"], norms))
+    sums = p.double().sum(dim=1).cpu().numpy()
+    assert np.abs(sums - target).max() < 1e-5
+    assert np.isfinite(float(lt[0]))
+    del probs
+
+
+def test_full_size_adjoint_closed_forms(h, big):
+    """At n=20, R=16, B=2000: sensitivity g = 1 gives alpha_r B psi_r and B ||psi_r||^2; g = (-1)^{u_j}
+    gives alpha_r sum_b sigma^(j)_{s_bj} psi_r (V^dagger diag(1,-1) V = sigma)."""
+    from paper_2607_19577_amd import api
+
+    inst = _big_inst(big)
+    n, B = 20, 2000
+    D = 1 << n
+    psi = big["atoms"].astype(np.complex128)
+    w = big["weights"]
+    ones = torch.ones((B, D), dtype=torch.float32, device=DEV)
+    _, ag, wg = api.qst_backward(h, [inst], grad_p=[ones])
+    torch.cuda.synchronize()
+    got = ag[0].cpu().numpy()
+    for r in (0, 7, 15):
+        assert close(got[r], w[r] * B * psi[r], TOL32), rel(got[r], w[r] * B * psi[r])
+    assert close(wg[0].cpu().numpy(), B * (np.abs(psi) ** 2).sum(axis=1), TOL32)
+    del ones
+    j = 13
+    bit = n - 1 - j
+    sign = 1.0 - 2.0 * ((torch.arange(D, device=DEV) >> bit) & 1).float()
+    gp = sign.expand(B, D).contiguous()
+    _, ag, _ = api.qst_backward(h, [inst], grad_p=[gp])
+    torch.cuda.synchronize()
+    got = ag[0].cpu().numpy()
+    counts = [int((big["settings"][:, j] == c).sum()) for c in (0, 1, 2)]
+    for r in (0, 9):
+        t = psi[r].reshape((2,) * n)
+        want = np.zeros(D, dtype=np.complex128)
+        for c in (0, 1, 2):
+            want += counts[c] * np.moveaxis(np.tensordot(pauli.SIGMA[c], t, axes=([1], [j])), 0, j).reshape(-1)
+        assert close(got[r], w[r] * want, TOL32), rel(got[r], w[r] * want)
+
+
+def test_full_size_gradient_on_setting_subset(h, big):
+    """The adjoint is a sum over settings: a 3-setting sub-instance at n=20, R=16 vs the oracle."""
+    from paper_2607_19577_amd import api
+
+    rows = [5, 1234, 1998]
+    case = dict(atoms=big["atoms"], weights=big["weights"], settings=big["settings"][rows].copy(),
+                freqs=big["freqs_dev"][rows].cpu().numpy())
+    ref = oracle(case, born.LOSS_CE, 1e-8, tier="axis")
+    _check(_run(h, case, api.LOSS_CE, api.PATH_BUTTERFLY_F32), ref, TOL32, "n=20 subset")
