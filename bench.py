@@ -1,0 +1,281 @@
+"""Benchmark of the hot path: fused forward map + adjoint on one MI355X.
+
+Workload (default): n = 20 qubits (D = 2^20), R = 16 atoms, B = 2000 random
+Pauli settings, 10^6 shots per setting, complex64 atoms, cross-entropy loss.
+One step = descriptor decode, the fused forward+adjoint pass (probabilities,
+loss, likelihood-ratio sensitivities, weight gradient, atom gradient with the
+tangent projection) and the FP64 coefficient step with pruning, with all
+inputs resident in HBM.  Metric: forward+adjoint atom-setting amplitudes per
+second (B * R * D per step).
+
+Also reported: the roofline of the dominant kernel (algorithmic bytes per
+launch over its event-timed duration), a CPU baseline of the FP64 oracle on a
+bounded sample of the same workload, the refactorisation time and the speedup
+over the plain one-pass-per-qubit reference path.
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBPS = 8000.0
+WORKLOADS = {
+    "n20_r16_b2000": dict(n=20, R=16, B=2000, shots=1_000_000, R_true=4),
+    "n14_r8_b1000": dict(n=14, R=8, B=1000, shots=100_000, R_true=4),
+    "n10_r4_b200": dict(n=10, R=4, B=200, shots=10_000, R_true=4),
+}
+KERNEL_SOURCES = ["paper_2607_19577_amd/csrc/qst_kernels.hip", "paper_2607_19577_amd/csrc/qst_device.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# ---------------------------------------------------------------- CPU baseline (oracle)
+_CPU = {}
+
+
+def _cpu_init():
+    from threadpoolctl import threadpool_limits
+
+    threadpool_limits(1)
+
+
+def _cpu_probs(task):
+    from oracle import born
+
+    b, r = task
+    return born.probs_axis(_CPU["atoms"][r:r + 1], _CPU["w"][r:r + 1], _CPU["s"], rows=[b])[0]
+
+
+def _cpu_grads(task):
+    from oracle import born
+
+    b, r = task
+    ga, gw = born.gradients_axis(_CPU["atoms"][r:r + 1], _CPU["w"][r:r + 1], _CPU["s"], _CPU["g"][[b]], rows=[b])
+    return float(gw[0])
+
+
+def cpu_baseline(atoms, w, s, B, shots, n_sample: int, seed: int):
+    """The FP64 oracle (per-axis tier) on n_sample settings x all atoms: probabilities, loss and
+    sensitivities, then the adjoint, split into (setting, atom) calls over a fork pool."""
+    from oracle import born
+
+    R = atoms.shape[0]
+    f = synth.porter_thomas_freqs(synth.make_rng(seed), n_sample, atoms.shape[1], synth.dirichlet_weights(
+        synth.make_rng(seed + 1), 4), shots)
+    _CPU.update(atoms=atoms.astype(np.complex128), w=w, s=s[:n_sample])
+    tasks = [(b, r) for b in range(n_sample) for r in range(R)]
+    cores = max(1, min(16, os.cpu_count() or 1, len(tasks)))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores, initializer=_cpu_init) as pool:
+        parts = pool.map(_cpu_probs, tasks)
+        p = np.zeros((n_sample, atoms.shape[1]))
+        for (b, _), q in zip(tasks, parts):
+            p[b] += q
+        _, g = born.loss_and_sensitivity(p, f, B, born.LOSS_CE, 1e-8)
+        _CPU["g"] = g
+    with ctx.Pool(cores, initializer=_cpu_init) as pool:
+        pool.map(_cpu_grads, tasks)
+    dt = time.perf_counter() - t0
+    amps = n_sample * R * atoms.shape[1]
+    return dict(value=amps / dt, unit="amplitudes/s", cores=cores, kind="oracle",
+                sample=f"{n_sample} of {B} settings x {R} atoms x D={atoms.shape[1]}: FP64 per-axis oracle "
+                       f"probabilities, CE loss and sensitivities, adjoint; {dt:.1f} s wall on {cores} processes")
+
+
+# ---------------------------------------------------------------- traffic file
+def read_traffic(kernel_kind: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_kind}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"<!--\s*traffic\s*(\{.*?\})\s*-->", txt, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return float(d["bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="n20_r16_b2000", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip refactor / plain-path timings")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--batch", type=int, default=0, help="settings per batch (0: library default)")
+    ap.add_argument("--copy-calibration", action="store_true", help="run only a 1 GiB device copy (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    wl = WORKLOADS[args.workload]
+    n, R, B, shots = wl["n"], wl["R"], wl["B"], wl["shots"]
+    D = 1 << n
+    seed = 20260101
+
+    if args.copy_calibration:
+        import torch
+
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 4}))
+        return
+
+    rng = synth.make_rng(seed)
+    atoms = synth.haar_atoms(rng, R, D, dtype=np.complex64)
+    w = synth.dirichlet_weights(rng, R)
+    s = synth.random_settings(rng, B, n)
+    w_true = synth.dirichlet_weights(rng, wl["R_true"])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_sample = 2 if n >= 18 else min(B, 64 if n <= 12 else 8)
+        cpu = cpu_baseline(atoms, w, s, B, shots, n_sample, seed + 7)
+        print(f"[bench] cpu baseline: {cpu['value']:.3e} amplitudes/s ({cpu['sample']})", file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_2607_19577_amd import api
+
+    dev = torch.device("cuda:0")
+    freqs = synth.porter_thomas_freqs_torch(seed + 3, B, D, w_true, shots, dev)
+    inst = api.Instance(torch.from_numpy(atoms).to(dev), torch.from_numpy(w).to(dev), torch.from_numpy(s).to(dev),
+                        freqs)
+    grad = torch.empty_like(inst.atoms)
+    h = api.Handle(0)
+    if args.autotune:
+        api.qst_plan(h, [inst], autotune=True)
+    print(f"[bench] inputs resident: atoms {inst.atoms.numel() * 8 / 2**20:.0f} MiB, freqs "
+          f"{freqs.numel() * 4 / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+
+    def step():
+        lt, ag, wg = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, project_tangent=True, out=[grad])
+        # coefficient step: beta = proj(alpha + eta (A^T c)) with A^T c = -dL/dalpha
+        api.qst_reweight_simplex(h, inst.weights, wg[0], -0.5, 1e-3)
+        return lt
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile(True)
+    h.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lt = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = h.profile_read(reset=True)
+    h.profile(False)
+    ms_per_step = elapsed * 1e3 / args.steps
+    amps = B * R * D
+    value = amps * args.steps / elapsed
+    print(f"[bench] {ms_per_step:.2f} ms/step, loss {float(lt[0]):.6f}, stages {stages}", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel
+    from paper_2607_19577_amd._lib import load  # noqa: F401
+
+    S = None
+    lo_launches = stages["lo_fused"][0]
+    if lo_launches:
+        S = B * args.steps / lo_launches  # settings per batch (uniform batches)
+    cb = 8  # bytes per complex64
+    per_launch_bytes = {
+        "hi_fwd": (R * D * cb + S * R * D * cb) if S else None,
+        "lo_fused": (S * R * D * cb + S * D * 4 + S * R * D * cb) if S else None,
+        "hi_adj": (S * R * D * cb + 2 * R * D * cb) if S else None,
+    }
+    dom = max(("hi_fwd", "lo_fused", "hi_adj"), key=lambda k: stages[k][1])
+    nl, tot_ms = stages[dom]
+    avg_ms = tot_ms / max(nl, 1)
+    achieved = per_launch_bytes[dom] / (avg_ms * 1e-3) / 1e9 if per_launch_bytes[dom] else None
+    names = {"hi_fwd": "k_stage_hi_fwd", "lo_fused": "k_stage_lo_fused", "hi_adj": "k_stage_hi_adj"}
+    traffic = read_traffic(names[dom], args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
+                "traffic": traffic, "kernel": names[dom], "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": per_launch_bytes[dom]}
+    model_bytes_step = sum((per_launch_bytes[k] or 0) * stages[k][0] for k in per_launch_bytes) / args.steps
+
+    extras = {}
+    if not args.no_extras:
+        # plain one-pass-per-qubit reference kernel on the same workload (one call)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=api.PATH_PLAIN_F32, out=[grad])
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3
+        extras["plain_path_ms"] = round(plain_ms, 1)
+        t0 = time.perf_counter()
+        api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, out=[grad])
+        torch.cuda.synchronize()
+        fused_ms = (time.perf_counter() - t0) * 1e3
+        extras["speedup_vs_plain"] = round(plain_ms / fused_ms, 2)
+        v0 = torch.from_numpy(synth.haar_atoms(synth.make_rng(seed + 11), 1, D)[0]).to(dev)
+        t0 = time.perf_counter()
+        res = api.qst_refactor(h, inst, api.LOSS_CE, 1e-8, 0.5, 1e-3, 1e-3, 8, 30, v0)
+        torch.cuda.synchronize()
+        extras["refactor_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+        extras["refactor_R_out"] = int(res["R"][0])
+
+    out = {
+        "metric": "fwd+adjoint atom-setting amplitudes/s",
+        "value": value,
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"n={n} qubits, R={R} atoms, B={B} random Pauli settings, {shots} shots/setting, "
+                               "complex64 atoms, cross-entropy", "n": n, "R": R, "B": B, "D": D,
+                   "settings_per_batch": S},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stage_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in stages.items()},
+        "model_hbm_bytes_per_step": model_bytes_step,
+        "model_GBps_whole_step": round(model_bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
+        "kernel_source_hash": kernel_source_hash(),
+        **extras,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

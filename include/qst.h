@@ -179,6 +179,18 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
                         void* atoms_out, double* weights_out, int32_t* R_out, int32_t* s_star,
                         double* ritz_vals, double* ritz_resid, double* q_scores, qst_path path);
 
+/* Per-stage timing of the hot path (measurement support; not needed for results).
+ * qst_profile_enable(h, 1) brackets every kernel launch the handle makes with a pair
+ * of HIP events on its stream, grouped by stage kind:
+ *   0 descriptor decode, 1 high-bit tile stage (forward), 2 fused low-bit stage,
+ *   3 high-bit tile stage (adjoint, gradient accumulation), 4 reductions and
+ *   epilogues, 5 other (reweight, refactor helpers, reference path).
+ * qst_profile_read synchronises the stream and returns, for one kind, the number of
+ * launches and their summed event-to-event milliseconds since the last reset
+ * (reset != 0 clears every kind).  Enabling allocates events: not during capture. */
+qst_status qst_profile_enable(qst_handle* h, int enable);
+qst_status qst_profile_read(qst_handle* h, int kind, int64_t* launches, double* total_ms, int reset);
+
 /* Library build information: a static string (architecture, version). */
 const char* qst_build_info(void);
 

@@ -25,6 +25,7 @@ PATH_AUTO, PATH_BUTTERFLY_F32, PATH_BUTTERFLY_F64, PATH_PLAIN_F32, PATH_TILE_F16
 EXPORTS = (
     "qst_create", "qst_destroy", "qst_set_stream", "qst_status_string", "qst_last_error", "qst_plan",
     "qst_forward", "qst_backward", "qst_reweight_simplex", "qst_refactor", "qst_build_info",
+    "qst_profile_enable", "qst_profile_read",
 )
 
 
@@ -76,6 +77,8 @@ def load() -> ctypes.CDLL:
     lib.qst_reweight_simplex.argtypes = [vp, vp, vp, ctypes.c_int, dbl, dbl, vp, vp, vp]
     lib.qst_refactor.argtypes = [vp, P(QstInstance), ctypes.c_int, dbl, dbl, dbl, dbl, ctypes.c_int, ctypes.c_int,
                                  vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
+    lib.qst_profile_enable.argtypes = [vp, ctypes.c_int]
+    lib.qst_profile_read.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(dbl), ctypes.c_int]
     for name in EXPORTS:
         if name not in ("qst_status_string", "qst_last_error", "qst_build_info"):
             getattr(lib, name).restype = ctypes.c_int

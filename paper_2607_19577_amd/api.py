@@ -50,6 +50,25 @@ class Handle:
     def set_stream(self, stream: torch.cuda.Stream) -> None:
         _lib.check(self.lib.qst_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), self.h)
 
+    def profile(self, enable: bool = True) -> None:
+        _lib.check(self.lib.qst_profile_enable(self.h, int(enable)), self.h)
+
+    STAGES = ("decode", "hi_fwd", "lo_fused", "hi_adj", "reduce", "other")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{stage: (launches, total_ms)} since the last reset (synchronises the stream)."""
+        out = {}
+        for k, name in enumerate(self.STAGES):
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            _lib.check(self.lib.qst_profile_read(self.h, k, ctypes.byref(n), ctypes.byref(ms), 0), self.h)
+            out[name] = (int(n.value), float(ms.value))
+        if reset:
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            _lib.check(self.lib.qst_profile_read(self.h, 0, ctypes.byref(n), ctypes.byref(ms), 1), self.h)
+        return out
+
     def close(self) -> None:
         if self.h:
             self.lib.qst_destroy(self.h)

@@ -29,11 +29,52 @@ struct qst_handle {
   hipEvent_t flag_ev = nullptr;
   bool flag_pending = false;
   std::map<std::tuple<int, int, int, int>, int> tuned_S;  // (n, R, B, path) -> settings per batch
+  // stage timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
+  struct Mark {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  int open_kind = -1;
+  hipEvent_t open_ev = nullptr;
 };
 
 namespace {
 
 constexpr int G1 = 256;  // first-level reduction width
+
+enum { PK_DECODE = 0, PK_HI_FWD = 1, PK_LO = 2, PK_HI_ADJ = 3, PK_REDUCE = 4, PK_OTHER = 5 };
+
+hipEvent_t prof_event(qst_handle* h) {
+  if (h->ev_next == h->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_next++];
+}
+
+// Bracket the next launch(es) of one stage kind.
+void prof_begin(qst_handle* h, int kind) {
+  if (!h->prof) return;
+  hipEvent_t e = prof_event(h);
+  if (!e) return;
+  hipEventRecord(e, h->stream);
+  h->open_kind = kind;
+  h->open_ev = e;
+}
+
+void prof_end(qst_handle* h) {
+  if (!h->prof || h->open_kind < 0) return;
+  hipEvent_t e = prof_event(h);
+  if (!e) return;
+  hipEventRecord(e, h->stream);
+  h->marks.push_back({h->open_kind, h->open_ev, e});
+  h->open_kind = -1;
+}
 
 qst_status set_err(qst_handle* h, qst_status s, const std::string& msg) {
   if (h) h->last_error = msg;
@@ -238,7 +279,9 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   double* sums = reinterpret_cast<double*>(ws + L.sums);
   hipStream_t s = h->stream;
 
+  prof_begin(h, PK_DECODE);
   QST_HIP(qst::launch_decode(in.settings, g.B, g.n, pc, h->dflag, s));
+  prof_end(h);
   const bool want_loss = rs.grad_p == nullptr && rs.loss_kind != QST_LOSS_NONE;
   const long long nslots = nslots_of(g, path);
 
@@ -266,6 +309,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
     const int Sb = std::min(S, g.B - b0);
     la.b0 = b0;
     if (path == QST_PATH_PLAIN_F32) {
+      prof_begin(h, PK_OTHER);
       QST_HIP(qst::launch_plain_copy(in.atoms, X, Sb, g.R, g.D, s));
       for (int bit = 0; bit < g.n; ++bit) QST_HIP(qst::launch_plain_qubit(X, Sb, g.R, g.D, bit, pc, b0, false, s));
       QST_HIP(qst::launch_plain_point(la, X, Sb, s));
@@ -273,6 +317,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
         for (int bit = 0; bit < g.n; ++bit) QST_HIP(qst::launch_plain_qubit(X, Sb, g.R, g.D, bit, pc, b0, true, s));
         QST_HIP(qst::launch_plain_sum(X, Sb, g.R, g.D, rs.atom_grad, b0 == 0, s));
       }
+      prof_end(h);
       continue;
     }
     const bool tile = path == QST_PATH_TILE_F16 || path == QST_PATH_TILE_BF16;
@@ -292,7 +337,9 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
       ha.b0 = b0;
       ha.S = Sb;
       ha.first = 0;
+      prof_begin(h, PK_HI_FWD);
       QST_HIP(tile ? qst::launch_tile_hi(g, ha, false, bf16, s) : qst::launch_stage_hi(g, ha, false, s));
+      prof_end(h);
       la.src = X;
       la.src_set_stride = (long long)g.R * g.D;
     } else {
@@ -300,7 +347,9 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
       la.src_set_stride = 0;
     }
     la.dst = W;
+    prof_begin(h, PK_LO);
     QST_HIP(tile ? qst::launch_tile_lo(g, la, Sb, rs.adjoint, bf16, s) : qst::launch_stage_lo(g, la, Sb, rs.adjoint, s));
+    prof_end(h);
     if (rs.adjoint) {
       if (g.n_hi > 0) {
         qst::HiArgs hc{};
@@ -317,12 +366,17 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
         hc.b0 = b0;
         hc.S = Sb;
         hc.first = b0 == 0;
+        prof_begin(h, PK_HI_ADJ);
         QST_HIP(tile ? qst::launch_tile_hi(g, hc, true, bf16, s) : qst::launch_stage_hi(g, hc, true, s));
+        prof_end(h);
       } else {
+        prof_begin(h, PK_HI_ADJ);
         QST_HIP(qst::launch_sum_settings(g, W, Sb, rs.atom_grad, b0 == 0, s));
+        prof_end(h);
       }
     }
   }
+  prof_begin(h, PK_REDUCE);
   if (want_loss || rs.adjoint) {
     const int rows = rs.adjoint ? g.R + 1 : 1;
     QST_HIP(qst::launch_rowsum(part, rows, nslots, lvl1, G1, sums, s));
@@ -336,6 +390,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   if (rs.adjoint && rs.project_tangent) {
     QST_HIP(qst::launch_tangent(g.elem, in.atoms, rs.atom_grad, g.R, g.D, reinterpret_cast<double*>(ws + L.tan), G1, s));
   }
+  prof_end(h);
   return QST_OK;
 }
 
@@ -418,6 +473,36 @@ const char* qst_status_string(qst_status s) {
   return "unknown status";
 }
 
+qst_status qst_profile_enable(qst_handle* h, int enable) {
+  if (!h) return QST_ERR_INVALID_ARG;
+  if (h->device < 0) return set_err(h, QST_ERR_UNSUPPORTED, "validation-only handle");
+  if (enable && capturing(h->stream)) return set_err(h, QST_ERR_CAPTURE, "enable profiling outside capture");
+  h->prof = enable != 0;
+  return QST_OK;
+}
+
+qst_status qst_profile_read(qst_handle* h, int kind, int64_t* launches, double* total_ms, int reset) {
+  if (!h || !launches || !total_ms) return QST_ERR_INVALID_ARG;
+  if (kind < 0 || kind > 5) return set_err(h, QST_ERR_INVALID_ARG, "kind must be in 0..5");
+  *launches = 0;
+  *total_ms = 0.0;
+  if (h->device < 0) return QST_OK;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return set_err(h, QST_ERR_DEVICE, "stream synchronise failed");
+  for (const auto& m : h->marks) {
+    if (m.kind != kind) continue;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+      *launches += 1;
+      *total_ms += ms;
+    }
+  }
+  if (reset) {
+    h->marks.clear();
+    h->ev_next = 0;
+  }
+  return QST_OK;
+}
+
 const char* qst_build_info(void) { return "qst gfx950 staged-butterfly/tile v1"; }
 
 const char* qst_last_error(const qst_handle* h) { return h ? h->last_error.c_str() : "null handle"; }
@@ -462,6 +547,7 @@ qst_status qst_destroy(qst_handle* h) {
   if (h->dflag) hipFree(h->dflag);
   if (h->hflag) hipHostFree(h->hflag);
   if (h->flag_ev) hipEventDestroy(h->flag_ev);
+  for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
   delete h;
   return QST_OK;
 }
