@@ -39,7 +39,8 @@ WORKLOADS = {
     "n14_r8_b1000": dict(n=14, R=8, B=1000, shots=100_000, R_true=4),
     "n10_r4_b200": dict(n=10, R=4, B=200, shots=10_000, R_true=4),
 }
-KERNEL_SOURCES = ["paper_2607_19577_amd/csrc/qst_kernels.hip", "paper_2607_19577_amd/csrc/qst_device.hpp"]
+KERNEL_SOURCES = ["paper_2607_19577_amd/csrc/qst_stages.hpp", "paper_2607_19577_amd/csrc/qst_device.hpp",
+                  "paper_2607_19577_amd/csrc/qst_kernels.hip"]
 
 
 def kernel_source_hash() -> str:

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libqst.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["qst_kernels.hip", "qst_tile.hip", "qst_api.hip"]
+SOURCES = ["qst_kernels.hip", "qst_lo_f32.hip", "qst_lo_f64.hip", "qst_hi.hip", "qst_tile.hip", "qst_api.hip"]
 
 # Packed-FP32 instructions are kept out of the device code on purpose.
 HIPFLAGS = [
@@ -42,7 +42,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link ``libqst.so``; always rebuilds."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]

@@ -20,6 +20,7 @@ using qst::Geometry;
 
 struct qst_handle {
   int device = 0;
+  int num_cu = 256;
   hipStream_t stream = nullptr;
   std::string last_error;
   void* ws = nullptr;  // workspace arena (grow-only)
@@ -152,9 +153,15 @@ qst_status make_geometry(qst_handle* h, int n, int R, int B, int elem, Geometry&
       return set_err(h, QST_ERR_UNSUPPORTED,
                      "n=" + std::to_string(n) + ", R=" + std::to_string(R) + " is outside the tile-stage shapes");
   }
-  g.cpw = std::min(4, 1 << g.n_hi);
-  g.items_per_setting = (1ll << g.n_hi) / g.cpw;
   return QST_OK;
+}
+
+// Persistent low-stage grid for batches of S settings.
+void set_grid(qst_handle* h, Geometry& g, int S) {
+  g.S = S;
+  const long long chunks = (long long)S << g.n_hi;
+  const long long resident = (long long)h->num_cu * (h->device >= 0 ? qst::lo_blocks_per_cu(g) : 1);
+  g.grid_lo = (int)std::max(1ll, std::min(chunks, resident));
 }
 
 int default_S(const Geometry& g) {
@@ -174,7 +181,8 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 long long nslots_of(const Geometry& g, qst_path path) {
   if (path == QST_PATH_PLAIN_F32) return (long long)g.B * ((g.D + 255) / 256);
-  return (long long)g.B * g.items_per_setting;
+  const long long batches = (g.B + g.S - 1) / g.S;
+  return batches * g.grid_lo;
 }
 
 WsLayout layout_ws(const Geometry& g, int S, qst_path path, bool with_gneg, size_t base = 0) {
@@ -265,7 +273,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
     auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)path));
     if (rs.S_override <= 0 && it != h->tuned_S.end()) S = std::min(it->second, g.B);
   }
-  g.S = S;
+  set_grid(h, g, S);
   const WsLayout L = layout_ws(g, S, path, false, ws_base);
   if (ws_end) *ws_end = L.total;
   st = ensure_ws(h, L.total);
@@ -300,7 +308,6 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   la.n_lo = g.n_lo;
   la.n_hi = g.n_hi;
   la.log_ta = g.n_lo - g.logv_lo;
-  la.cpw = g.cpw;
   la.B = g.B;
   la.loss_kind = rs.grad_p ? 2 : (int)rs.loss_kind;
   la.eps = rs.eps;
@@ -308,6 +315,8 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   for (int b0 = 0; b0 < g.B; b0 += S) {
     const int Sb = std::min(S, g.B - b0);
     la.b0 = b0;
+    la.slot_base = (long long)(b0 / S) * g.grid_lo;
+    la.nchunks = Sb << g.n_hi;
     if (path == QST_PATH_PLAIN_F32) {
       prof_begin(h, PK_OTHER);
       QST_HIP(qst::launch_plain_copy(in.atoms, X, Sb, g.R, g.D, s));
@@ -523,6 +532,11 @@ qst_status qst_create(int device, void* hip_stream, qst_handle** out) {
   qst_handle* h = new qst_handle();
   h->device = device;
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+      h->num_cu = prop.multiProcessorCount;
+  }
   if (hipMalloc(&h->dflag, sizeof(int)) != hipSuccess || hipHostMalloc(&h->hflag, sizeof(int)) != hipSuccess ||
       hipEventCreateWithFlags(&h->flag_ev, hipEventDisableTiming) != hipSuccess) {
     delete h;
@@ -643,6 +657,7 @@ qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_pat
       S = best_S;
       h->tuned_S[std::make_tuple(g.n, g.R, g.B, (int)path)] = S;
     }
+    set_grid(h, g, std::min(S, g.B));
     need = std::max(need, layout_ws(g, std::min(S, g.B), path, false).total);
   }
   st = device_gate(h);
@@ -784,9 +799,10 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
 
   // Workspace: [run region for R atoms | run region for one vector | gneg | Krylov Q | w | vin | gv | A128 | misc]
   const int SR = default_S(gR);
-  gR.S = SR;
+  set_grid(h, gR, SR);
   const WsLayout LR = layout_ws(gR, SR, path, true, 0);
   const int S1 = default_S(g1);
+  set_grid(h, g1, S1);
   const WsLayout L1 = layout_ws(g1, S1, path, false, al256(LR.total));
   size_t o = al256(L1.total);
   const size_t off_Q = o;

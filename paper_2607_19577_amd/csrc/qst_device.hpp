@@ -181,6 +181,69 @@ __device__ __forceinline__ void xform_uniform(T (&x)[1 << LOGV], T (&y)[1 << LOG
   xform_uniform_bit<0, LOGV, ADJ, ACTIVE>(x, y, codes);
 }
 
+// Phase-split form (used by the staged kernels).  V_Y = H diag(1, -i) with the
+// diagonal on the input side, and diagonals on different qubits commute with
+// everything else, so for a setting with Y-qubit mask ymask
+//     V_b = (x)_k M_k  *  diag((-i)^popcount(v & ymask)),
+// M_k = H for X and Y bits and, as above, diag(1,-1) for Z bits (a row phase).
+// The kernels apply the per-element phase once per setting where the state
+// enters the rotation (forward) or leaves it (adjoint: the conjugate phase
+// after the M's), and every bit in between takes the same 4-operation
+// butterfly a' = a + f b, b' = f a - b with f = [code != Z]; H and diag(1,-1)
+// are their own adjoints.
+template <int K, int LOGV, typename T>
+__device__ __forceinline__ void bit_xz(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t c) {
+  const T f = c < 2u ? T(1) : T(0);
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) {
+    if (i & (1 << K)) continue;
+    const int j = i | (1 << K);
+    const T ax = x[i], ay = y[i];
+    x[i] = fma(f, x[j], ax);
+    y[i] = fma(f, y[j], ay);
+    x[j] = fma(f, ax, -x[j]);
+    y[j] = fma(f, ay, -y[j]);
+  }
+}
+
+template <int K, int LOGV, uint32_t ACTIVE, typename T>
+__device__ __forceinline__ void xform_xz_bit(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
+  if constexpr (K < LOGV) {
+    if constexpr ((ACTIVE >> K) & 1u) bit_xz<K, LOGV>(x, y, (codes >> (2 * K)) & 3u);
+    xform_xz_bit<K + 1, LOGV, ACTIVE>(x, y, codes);
+  }
+}
+
+template <int LOGV, uint32_t ACTIVE, typename T>
+__device__ __forceinline__ void xform_xz(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
+  xform_xz_bit<0, LOGV, ACTIVE>(x, y, codes);
+}
+
+// Index-bit mask of the Y qubits of a decoded setting.
+__device__ __forceinline__ uint32_t ymask_of(uint64_t pc, int n) {
+  uint32_t m = 0;
+  for (int q = 0; q < n; ++q)
+    if (((pc >> (2 * q)) & 3ull) == 1ull) m |= 1u << q;
+  return __builtin_amdgcn_readfirstlane(m);
+}
+
+// (x + i y) <- (x + i y) * (-i)^k  (forward)  or  * (+i)^k  (CONJ), k = kk & 3:
+//   (-i)^k: k=1 (y, -x), k=2 (-x, -y), k=3 (-y, x);  (+i)^k: k=1 (-y, x), k=3 (y, -x).
+// Odd k exchanges the components; the forward phase negates x' for k in {2,3}
+// and y' for k in {1,2}, the conjugate one the other way round.
+template <bool CONJ, typename T>
+__device__ __forceinline__ void rot_k(T& x, T& y, uint32_t kk) {
+  const bool sw = (kk & 1u) != 0u;
+  const T xs = sw ? y : x;
+  const T ys = sw ? x : y;
+  const bool n_a = (kk & 2u) != 0u;          // k in {2,3}
+  const bool n_b = ((kk + 1u) & 2u) != 0u;   // k in {1,2}
+  const bool nx = CONJ ? n_b : n_a;
+  const bool ny = CONJ ? n_a : n_b;
+  x = nx ? -xs : xs;
+  y = ny ? -ys : ys;
+}
+
 // Code word of the layout `lo` for the bits [from, to) of the block, where
 // block bit q is index bit gbit0 + (q - qbase) of the state (q >= qbase).
 // Bits outside [from, to) are skipped.

@@ -11,17 +11,17 @@ namespace qst {
 //   n_hi : high qubits (bits [n_lo, n)), handled by the tile stages A and C.
 //   t, c : the tile stages hold 2^t amplitudes of one atom: 2^n_hi rows (stride
 //          2^n_lo) by 2^c contiguous columns, t = n_hi + c.
-//   cpw  : low-stage chunks (of 2^n_lo amplitudes) per work-group.
+//   grid_lo : work-groups of the persistent low stage (one launch per batch); each
+//          takes every grid_lo-th chunk (one setting x 2^n_lo outcomes, all atoms).
 //   S    : settings per batch (X and W hold S x R x D amplitudes).
 struct Geometry {
   int n, R, B;
   long long D;
   int n_lo, n_hi, t, c;
   int logv_lo;  // registers per thread in the low stage: 2^logv_lo
-  int cpw;
+  int grid_lo;
   int S;
   int elem;      // bytes per real (4 or 8)
-  long long items_per_setting;  // low-stage work-groups per setting = 2^n_hi / cpw
 };
 
 struct LoArgs {
@@ -36,8 +36,10 @@ struct LoArgs {
   void* gneg;                 // [B][D] or null: receives -dL/dp
   double* part;               // [(R+1)][nslots]: row 0 loss, rows 1..R weight gradient
   long long nslots;
+  long long slot_base;        // first slot of this launch (batch index x grid)
+  int nchunks;                // chunks in this launch: settings of the batch x 2^n_hi
   long long D;
-  int R, n, n_lo, n_hi, log_ta, cpw, b0, B;
+  int R, n, n_lo, n_hi, log_ta, b0, B;
   int loss_kind;
   double eps;
 };
@@ -88,6 +90,7 @@ hipError_t launch_tile_lo(const Geometry& g, const LoArgs& a, int S, bool adjoin
 hipError_t launch_tile_hi(const Geometry& g, const HiArgs& a, bool adjoint, bool bf16, hipStream_t st);
 
 size_t lo_lds_bytes(const Geometry& g);
+int lo_blocks_per_cu(const Geometry& g);
 size_t hi_lds_bytes(const Geometry& g);
 
 }  // namespace qst

@@ -1,22 +1,9 @@
-// HIP kernels of the staged butterfly path (gfx950).
-//
-// Forward map and adjoint of the atomic Born map over Pauli settings
-// (eqs. atomic-born-map, qst-loss, likelihood-ratio-vector, weight-gradient,
-// atom-wirtinger-gradient).  For setting b the rotation V_b = (x)_j V_{s_bj}
-// factors over index bits, so it is applied as unscaled butterflies, one per
-// non-Z qubit, with the exact scale 2^(-k_b) (k_b = non-Z count) put on |phi|^2.
-//
-// A state of D = 2^n amplitudes is split into low bits [0, n_lo) and high bits
-// [n_lo, n).  Per batch of S settings:
-//   stage A  (tile, high bits)   X[s][r] = V_b,high psi_r        (psi tile reused for S settings)
-//   stage B  (chunk, low bits)   phi = V_b,low X;  p = 2^-k sum_r alpha_r |phi_r|^2;
-//                                loss, g = dL/dp;  weight-gradient partials;
-//                                W[s][r] = V_b,low^dagger (alpha_r 2^-k g * phi_r)
-//   stage C  (tile, high bits)   grad_r += sum_s V_b,high^dagger W[s][r]
-// Stage B holds all R atoms of a chunk on chip, so p, g and the adjoint are
-// fused; stages A and C amortise the psi read and the gradient
-// read-modify-write over the S settings of a batch.  All reductions are
-// written to per-work-group slots and summed in a fixed order (deterministic).
+// Small kernels of the hot path: descriptor decode, fills, the per-setting
+// sums of the single-chunk geometry, deterministic reductions, the tangent
+// projection, the FP64 coefficient step, the plain one-pass-per-qubit
+// reference path and the vector helpers of the refactorisation.  The staged
+// transform kernels are templates in qst_stages.hpp, instantiated in
+// qst_lo_f32.hip, qst_lo_f64.hip and qst_hi.hip.
 #include "qst_device.hpp"
 #include "qst_internal.hpp"
 
@@ -77,372 +64,24 @@ size_t lo_lds_bytes(const Geometry& g) {
   return planes + nthr * sizeof(double);
 }
 
-// Transpose the registers of a thread between two layouts through LDS; the
-// real and imaginary parts use separate planes (padded indexing; both
-// layouts are compile-time).
-template <int LOGV, int LO_FROM, int LO_TO, typename T>
-__device__ __forceinline__ void lds_transpose(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau) {
-  T* rw = re + pad_base<LOGV, LO_FROM>(tau);
-  T* iw = im + pad_base<LOGV, LO_FROM>(tau);
-#pragma unroll
-  for (int i = 0; i < (1 << LOGV); ++i) {
-    rw[pad_off<LO_FROM>(i)] = x[i];
-    iw[pad_off<LO_FROM>(i)] = y[i];
-  }
-  __syncthreads();
-  const T* rr = re + pad_base<LOGV, LO_TO>(tau);
-  const T* ir = im + pad_base<LOGV, LO_TO>(tau);
-#pragma unroll
-  for (int i = 0; i < (1 << LOGV); ++i) {
-    x[i] = rr[pad_off<LO_TO>(i)];
-    y[i] = ir[pad_off<LO_TO>(i)];
-  }
-  __syncthreads();
+// ------------------------------------------------------------------ stage dispatch
+hipError_t launch_stage_lo_f32(const Geometry& g, const LoArgs& a, bool adjoint, hipStream_t st);
+hipError_t launch_stage_lo_f64(const Geometry& g, const LoArgs& a, bool adjoint, hipStream_t st);
+int lo_occupancy_f32(const Geometry& g);
+int lo_occupancy_f64(const Geometry& g);
+
+hipError_t launch_stage_lo(const Geometry& g, const LoArgs& a, int, bool adjoint, hipStream_t st) {
+  return g.elem == 4 ? launch_stage_lo_f32(g, a, adjoint, st) : launch_stage_lo_f64(g, a, adjoint, st);
 }
 
-// Forward chain: layout 0 (already loaded) .. last, transforming each layout's new bits.
-template <int K, typename CH, int LOGV, typename T>
-__device__ __forceinline__ void fwd_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc) {
-  if constexpr (K < CH::count()) {
-    if constexpr (K > 0) lds_transpose<LOGV, CH::lo(K - 1), CH::lo(K)>(x, y, re, im, tau);
-    xform<LOGV, false>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
-    fwd_chain<K + 1, CH, LOGV>(x, y, re, im, tau, pc);
-  }
-}
+// Resident low-stage work-groups per compute unit (the persistent grid is this
+// times the number of compute units).
+int lo_blocks_per_cu(const Geometry& g) { return g.elem == 4 ? lo_occupancy_f32(g) : lo_occupancy_f64(g); }
 
-// Adjoint chain: from the last layout back to layout 0.
-template <int K, typename CH, int LOGV, typename T>
-__device__ __forceinline__ void adj_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc) {
-  xform<LOGV, true>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
-  if constexpr (K > 0) {
-    lds_transpose<LOGV, CH::lo(K), CH::lo(K - 1)>(x, y, re, im, tau);
-    adj_chain<K - 1, CH, LOGV>(x, y, re, im, tau, pc);
-  }
-}
-
-template <typename T, int N_LO, bool ADJ>
-__global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
-  using C2 = cx<T>;
-  constexpr int LOGV = N_LO < 5 ? N_LO : 5;
-  constexpr int V = 1 << LOGV;
-  constexpr int U = 1 << N_LO;
-  constexpr int UPAD = U + (U >> 5);
-  constexpr int LOG_TA = N_LO - LOGV;
-  constexpr int TA = 1 << LOG_TA;
-  using CH = Chain<N_LO, LOGV>;
-  constexpr int NL = CH::count();
-  constexpr int LO0 = CH::lo(0);
-  constexpr uint32_t CB = sizeof(C2);
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  const int atom = tid >> LOG_TA;
-  const int tau = tid & (TA - 1);
-  const long long D = a.D;
-  const int per_set = (1 << a.n_hi) / a.cpw;
-  const int s = blockIdx.x / per_set;
-  const int hg = blockIdx.x - s * per_set;
-  const int b = a.b0 + s;
-  const uint64_t pc = uniform_u64(a.pc[b]);
-  const int kb = nonz_count(pc, a.n);
-  const T s2 = (T)ldexp(1.0, -kb);
-  const long long slot = (long long)b * per_set + hg;
-  const double Bd = (double)a.B;
-
-  // LDS: per atom a real and an imaginary plane of UPAD entries (transposes).  The
-  // |phi|^2 table [R][UPAD] and the sensitivity row g [UPAD] alias the first R+1 rows
-  // of the planes (2R rows in all); barriers separate their uses from the transposes.
-  T* planes = reinterpret_cast<T*>(smem);
-  T* re = planes + (size_t)atom * 2 * UPAD;
-  T* im = re + UPAD;
-  T* qb = planes;
-  T* gb = planes + (size_t)a.R * UPAD;
-  double* red = reinterpret_cast<double*>(smem + (((2 * (size_t)a.R * UPAD * sizeof(T)) + 15) & ~(size_t)15));
-
-  const T al = (T)a.alpha[atom];
-  const uint32_t vbytes = (uint32_t)(((long long)(a.R - 1) * D + U) * CB);
-  const uint32_t vo0 = (uint32_t)(((long long)atom * D + lay_pos<LOGV>(tau, 0, LO0)) * CB);
-  double loss_acc = 0.0, h_acc = 0.0;
-
-  for (int cc = 0; cc < a.cpw; ++cc) {
-    const int h = hg * a.cpw + cc;
-    const C2* sbase = reinterpret_cast<const C2*>(a.src) + (long long)s * a.src_set_stride + ((long long)h << N_LO);
-    const rsrc_t rs = make_rsrc(sbase, vbytes);
-    T x[V], y[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      C2 t;
-      bload(t, rs, vo0, (uint32_t)(i << LO0) * CB);
-      x[i] = t.x;
-      y[i] = t.y;
-    }
-    fwd_chain<0, CH, LOGV>(x, y, re, im, tau, pc);
-    // Final layout is lo = 0: alpha_r |phi_r|^2 into LDS, reduced over atoms per outcome.
-    T* qrow = qb + (size_t)atom * UPAD + pad_base<LOGV, 0>(tau);
-#pragma unroll
-    for (int i = 0; i < V; ++i) qrow[pad_off<0>(i)] = al * (x[i] * x[i] + y[i] * y[i]);
-    __syncthreads();
-    for (int u = tid; u < U; u += nthr) {
-      T p = 0;
-      for (int r = 0; r < a.R; ++r) p += qb[(size_t)r * UPAD + pad32(u)];
-      p *= s2;
-      const long long gi = (long long)b * D + ((long long)h << N_LO) + u;
-      if (a.probs) reinterpret_cast<T*>(a.probs)[gi] = p;
-      T g = 0;
-      if (a.grad_p) {
-        g = reinterpret_cast<const T*>(a.grad_p)[gi];
-      } else if (a.loss_kind == 0) {
-        const double f = (double)a.freqs[gi];
-        if (f > 0.0) {
-          const double piv = (double)p / Bd + a.eps;
-          loss_acc -= (f / Bd) * log(piv);
-          g = (T)(-(f / Bd) / piv / Bd);
-        }
-      } else if (a.loss_kind == 1) {
-        const double rr = ((double)p - (double)a.freqs[gi]) / Bd;
-        loss_acc += 0.5 * rr * rr;
-        g = (T)(rr / Bd);
-      }
-      if (a.gneg) reinterpret_cast<T*>(a.gneg)[gi] = -g;
-      if (ADJ) gb[pad32(u)] = g * s2;
-    }
-    __syncthreads();
-    if (ADJ) {
-      T hl = 0;
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        const T gv = gb[pad_base<LOGV, 0>(tau) + pad_off<0>(i)];
-        hl += gv * (x[i] * x[i] + y[i] * y[i]);
-        const T sc = al * gv;
-        x[i] *= sc;
-        y[i] *= sc;
-      }
-      h_acc += (double)hl;
-      __syncthreads();  // every thread has read g before the planes are reused
-      adj_chain<NL - 1, CH, LOGV>(x, y, re, im, tau, pc);
-      C2* dbase = reinterpret_cast<C2*>(a.dst) + (long long)s * a.R * D + ((long long)h << N_LO);
-      const rsrc_t rd = make_rsrc(dbase, vbytes);
-#pragma unroll
-      for (int i = 0; i < V; ++i) bstore(C2{x[i], y[i]}, rd, vo0, (uint32_t)(i << LO0) * CB);
-      __syncthreads();
-    }
-  }
-  if (a.part == nullptr) return;
-  if (ADJ) {
-    red[tid] = h_acc;
-    __syncthreads();
-    for (int st = TA >> 1; st > 0; st >>= 1) {
-      if (tau < st) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    if (tau == 0) a.part[(long long)(1 + atom) * a.nslots + slot] = red[tid];
-    __syncthreads();
-  }
-  if (a.grad_p == nullptr && a.loss_kind != 2) {
-    red[tid] = loss_acc;
-    __syncthreads();
-    int np2 = 1;
-    while (np2 < nthr) np2 <<= 1;
-    for (int st = np2 >> 1; st > 0; st >>= 1) {
-      if (tid < st && tid + st < nthr) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    if (tid == 0) a.part[slot] = red[0];
-  }
-}
-
-template <typename T, int N_LO>
-static hipError_t launch_lo_n(const Geometry& g, const LoArgs& a, int S, bool adjoint, hipStream_t st) {
-  constexpr int LOGV = N_LO < 5 ? N_LO : 5;
-  const int nthr = g.R << (N_LO - LOGV);
-  const size_t lds = lo_lds_bytes(g);
-  const unsigned grid = (unsigned)(S * g.items_per_setting);
-  if (adjoint) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_lo<T, N_LO, true><<<grid, nthr, lds, st>>>(a);
-  } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, false>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_lo<T, N_LO, false><<<grid, nthr, lds, st>>>(a);
-  }
-  return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t launch_lo_v(const Geometry& g, const LoArgs& a, int S, bool adjoint, hipStream_t st) {
-  switch (g.n_lo) {
-    case 1: return launch_lo_n<T, 1>(g, a, S, adjoint, st);
-    case 2: return launch_lo_n<T, 2>(g, a, S, adjoint, st);
-    case 3: return launch_lo_n<T, 3>(g, a, S, adjoint, st);
-    case 4: return launch_lo_n<T, 4>(g, a, S, adjoint, st);
-    case 5: return launch_lo_n<T, 5>(g, a, S, adjoint, st);
-    case 6: return launch_lo_n<T, 6>(g, a, S, adjoint, st);
-    case 7: return launch_lo_n<T, 7>(g, a, S, adjoint, st);
-    case 8: return launch_lo_n<T, 8>(g, a, S, adjoint, st);
-    case 9: return launch_lo_n<T, 9>(g, a, S, adjoint, st);
-    case 10: return launch_lo_n<T, 10>(g, a, S, adjoint, st);
-    case 11: return launch_lo_n<T, 11>(g, a, S, adjoint, st);
-    case 12: return launch_lo_n<T, 12>(g, a, S, adjoint, st);
-    case 13: return launch_lo_n<T, 13>(g, a, S, adjoint, st);
-    case 14: return launch_lo_n<T, 14>(g, a, S, adjoint, st);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_stage_lo(const Geometry& g, const LoArgs& a, int S, bool adjoint, hipStream_t st) {
-  return g.elem == 4 ? launch_lo_v<float>(g, a, S, adjoint, st) : launch_lo_v<double>(g, a, S, adjoint, st);
-}
-
-// ------------------------------------------------------------------ stages A and C
 size_t hi_lds_bytes(const Geometry& g) {
   const size_t N = (size_t)1 << g.t;
   return (N + (N >> 5)) * 2 * (size_t)g.elem;
 }
-
-// Offset (elements from the tile origin) of tile position lam: tile bits below c
-// are columns (index bits 0..c-1), the rest are rows (index bits n_lo..).
-__device__ __forceinline__ uint32_t tile_off(uint32_t lam, int c, int n_lo) {
-  return ((lam >> c) << n_lo) | (lam & ((1u << c) - 1u));
-}
-
-// Mask of the register bits of layout `lo` that are tile rows (qubits of the
-// high pass) and are transformed in this layout: bits [max(lo, c), top).
-constexpr uint32_t rows_mask(int lo, int c, int top) {
-  uint32_t m = 0;
-  for (int k = 0; k < 5; ++k)
-    if (lo + k >= c && lo + k < top) m |= 1u << k;
-  return m;
-}
-
-template <int TB, int N_HI, bool ADJ>
-__global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
-  using T = float;
-  using C2 = float2;
-  constexpr int LOGV = 5;
-  constexpr int V = 1 << LOGV;
-  constexpr int C = TB - N_HI;           // column bits of the tile
-  constexpr int LO0 = TB - LOGV;
-  constexpr bool TWO = C < LO0;          // rows reach below the first layout
-  constexpr int LO1 = TB - 2 * LOGV > 0 ? TB - 2 * LOGV : 0;
-  constexpr int LOF = TWO ? LO1 : LO0;
-  constexpr uint32_t M0 = rows_mask(LO0, C, TB);
-  constexpr uint32_t M1 = rows_mask(LO1, C, LO0);
-  constexpr int NPAD = (1 << TB) + (1 << (TB - 5));
-  constexpr uint32_t CB = sizeof(C2);
-  static_assert(!TWO || TB - 2 * LOGV >= 0 || C >= 0, "tile layouts");
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* re = reinterpret_cast<T*>(smem);
-  T* im = re + NPAD;
-  const int tid = threadIdx.x;
-  const int n_lo = a.n_lo;
-  const int ncb = 1 << (n_lo - C);
-  const int r = blockIdx.x / ncb;
-  const int cb = blockIdx.x - r * ncb;
-  const long long D = a.D;
-  const long long origin = (long long)r * D + ((long long)cb << C);
-  const uint32_t vbytes = (uint32_t)((D - ((long long)cb << C)) * CB);
-  const uint32_t vo0 = tile_off(lay_pos<LOGV>(tid, 0, LO0), C, n_lo) * CB;
-  const uint32_t vof = tile_off(lay_pos<LOGV>(tid, 0, LOF), C, n_lo) * CB;
-
-  if (!ADJ) {
-    const rsrc_t rs = make_rsrc(reinterpret_cast<const C2*>(a.src) + origin, vbytes);
-    T kx[V], ky[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      C2 t;
-      bload(t, rs, vo0, tile_off((uint32_t)i << LO0, C, n_lo) * CB);
-      kx[i] = t.x;
-      ky[i] = t.y;
-    }
-    for (int s = 0; s < a.S; ++s) {
-      const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
-      T x[V], y[V];
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        x[i] = kx[i];
-        y[i] = ky[i];
-      }
-      xform_uniform<LOGV, false, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
-      if constexpr (TWO) {
-        lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
-        xform_uniform<LOGV, false, M1>(x, y, layout_codes<LOGV>(pc, LO1, LO1, LO0, C, n_lo));
-      }
-      const rsrc_t rx = make_rsrc(reinterpret_cast<C2*>(a.dst) + (long long)s * a.R * D + origin, vbytes);
-#pragma unroll
-      for (int i = 0; i < V; ++i) bstore(C2{x[i], y[i]}, rx, vof, tile_off((uint32_t)i << LOF, C, n_lo) * CB);
-    }
-  } else {
-    T ax[V], ay[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) ax[i] = ay[i] = T(0);
-    for (int s = 0; s < a.S; ++s) {
-      const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
-      const rsrc_t rw = make_rsrc(reinterpret_cast<const C2*>(a.src) + (long long)s * a.R * D + origin, vbytes);
-      T x[V], y[V];
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        C2 t;
-        bload(t, rw, vo0, tile_off((uint32_t)i << LO0, C, n_lo) * CB);
-        x[i] = t.x;
-        y[i] = t.y;
-      }
-      xform_uniform<LOGV, true, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
-      if constexpr (TWO) {
-        lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
-        xform_uniform<LOGV, true, M1>(x, y, layout_codes<LOGV>(pc, LO1, LO1, LO0, C, n_lo));
-      }
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        ax[i] += x[i];
-        ay[i] += y[i];
-      }
-    }
-    const rsrc_t rg = make_rsrc(reinterpret_cast<C2*>(a.dst) + origin, vbytes);
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      const uint32_t so = tile_off((uint32_t)i << LOF, C, n_lo) * CB;
-      if (!a.first) {
-        C2 t;
-        bload(t, rg, vof, so);
-        ax[i] += t.x;
-        ay[i] += t.y;
-      }
-      bstore(C2{ax[i], ay[i]}, rg, vof, so);
-    }
-  }
-}
-
-template <int TB, int N_HI>
-static hipError_t launch_hi_n(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st) {
-  const int nthr = 1 << (TB - 5);
-  const size_t lds = hi_lds_bytes(g);
-  const unsigned grid = (unsigned)(g.R << (g.n_lo - g.c));
-  if (adjoint) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, true>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_hi<TB, N_HI, true><<<grid, nthr, lds, st>>>(a);
-  } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, false>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_hi<TB, N_HI, false><<<grid, nthr, lds, st>>>(a);
-  }
-  return hipGetLastError();
-}
-
-// Supported (tile bits, high bits) pairs of the FP32 path: n in 11..20 with the
-// low-stage sizes chosen by the host (n_lo >= 10).
-hipError_t launch_stage_hi(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st) {
-  if (g.elem != 4) return hipErrorInvalidValue;
-#define QST_HI(TBv, NHv) \
-  if (g.t == TBv && g.n_hi == NHv) return launch_hi_n<TBv, NHv>(g, a, adjoint, st);
-  QST_HI(14, 1) QST_HI(14, 2) QST_HI(14, 3) QST_HI(14, 4) QST_HI(14, 5)
-  QST_HI(14, 6) QST_HI(14, 7) QST_HI(14, 8) QST_HI(14, 9) QST_HI(14, 10)
-  QST_HI(13, 1) QST_HI(13, 2) QST_HI(13, 3) QST_HI(12, 1) QST_HI(12, 2) QST_HI(11, 1)
-#undef QST_HI
-  return hipErrorInvalidValue;
-}
-
 
 // ------------------------------------------------------------------ sum over settings (no high bits)
 template <typename T>

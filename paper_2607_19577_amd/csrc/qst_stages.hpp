@@ -1,0 +1,459 @@
+// Kernel templates of the staged butterfly path (gfx950).
+//
+// Forward map and adjoint of the atomic Born map over Pauli settings
+// (eqs. atomic-born-map, qst-loss, likelihood-ratio-vector, weight-gradient,
+// atom-wirtinger-gradient).  For setting b the rotation V_b = (x)_j V_{s_bj}
+// factors over index bits; it is applied in the phase-split form of
+// qst_device.hpp: one per-element Y phase plus one 4-operation butterfly per
+// qubit, with the exact scale 2^(-k_b) (k_b = non-Z count) put on |phi|^2.
+//
+// A state of D = 2^n amplitudes is split into low bits [0, n_lo) and high bits
+// [n_lo, n).  Per batch of S settings:
+//   stage A  (tile, high bits)   X[s][r] = M_high P psi_r   (P: all Y phases; psi tile kept for S settings)
+//   stage B  (chunk, low bits)   phi = M_low X;  p = 2^-k sum_r alpha_r |phi_r|^2;
+//                                loss, g = dL/dp;  weight-gradient partials;
+//                                W[s][r] = M_low (alpha_r 2^-k g * phi_r)
+//   stage C  (tile, high bits)   grad_r += sum_s P^dagger M_high W[s][r]
+// Stage B holds all R atoms of a chunk on chip, so p, g and the adjoint are
+// fused; stages A and C amortise the psi read and the gradient
+// read-modify-write over the S settings of a batch.  When n = n_lo the state
+// is one chunk and stage B applies the phases itself.  All reductions are
+// written to per-work-group slots and summed in a fixed order (deterministic).
+#pragma once
+#include "qst_device.hpp"
+#include "qst_internal.hpp"
+
+namespace qst {
+
+// Transpose the registers of a thread between two layouts through LDS; the
+// real and imaginary parts use separate planes (padded indexing; both
+// layouts are compile-time).
+template <int LOGV, int LO_FROM, int LO_TO, typename T>
+__device__ __forceinline__ void lds_transpose(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau) {
+  T* rw = re + pad_base<LOGV, LO_FROM>(tau);
+  T* iw = im + pad_base<LOGV, LO_FROM>(tau);
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) {
+    rw[pad_off<LO_FROM>(i)] = x[i];
+    iw[pad_off<LO_FROM>(i)] = y[i];
+  }
+  __syncthreads();
+  const T* rr = re + pad_base<LOGV, LO_TO>(tau);
+  const T* ir = im + pad_base<LOGV, LO_TO>(tau);
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) {
+    x[i] = rr[pad_off<LO_TO>(i)];
+    y[i] = ir[pad_off<LO_TO>(i)];
+  }
+  __syncthreads();
+}
+
+// Register bits of layout K of a chain that are new there (bits [lo(K), top(K))).
+template <typename CH, int K>
+constexpr uint32_t chain_mask() {
+  uint32_t m = 0;
+  for (int k = 0; k < 5; ++k)
+    if (CH::lo(K) + k < CH::top(K)) m |= 1u << k;
+  return m;
+}
+
+// Butterflies of every layout of the chain, first to last.
+template <int K, typename CH, int LOGV, typename T>
+__device__ __forceinline__ void fwd_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc) {
+  if constexpr (K < CH::count()) {
+    if constexpr (K > 0) lds_transpose<LOGV, CH::lo(K - 1), CH::lo(K)>(x, y, re, im, tau);
+    xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
+    fwd_chain<K + 1, CH, LOGV>(x, y, re, im, tau, pc);
+  }
+}
+
+// The same butterflies from the last layout back to layout 0 (each is its own adjoint).
+template <int K, typename CH, int LOGV, typename T>
+__device__ __forceinline__ void adj_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc) {
+  xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
+  if constexpr (K > 0) {
+    lds_transpose<LOGV, CH::lo(K), CH::lo(K - 1)>(x, y, re, im, tau);
+    adj_chain<K - 1, CH, LOGV>(x, y, re, im, tau, pc);
+  }
+}
+
+// Apply the Y phase (or its conjugate) to the registers of one layout: register i
+// of this thread holds index base_index | off(i), with off(i) uniform, so the
+// exponent is popcount(base & ym) (per lane) + popcount(off(i) & ym) (uniform).
+template <bool CONJ, int LOGV, typename T, typename OffFn>
+__device__ __forceinline__ void apply_phase(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t base_index, uint32_t ym,
+                                            OffFn off) {
+  const uint32_t mt = (uint32_t)__popc(base_index & ym);
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) {
+    const uint32_t mi = __builtin_amdgcn_readfirstlane((uint32_t)__popc(off(i) & ym));
+    rot_k<CONJ>(x[i], y[i], mt + mi);
+  }
+}
+
+// ------------------------------------------------------------------ stage B
+// Persistent low stage: work-group w takes chunks w, w + G, w + 2G, ... of the
+// batch (chunk = one setting x 2^n_lo consecutive outcomes, all atoms) and
+// prefetches the next chunk's amplitudes and data row while it works on the
+// current one.  Its loss and weight-gradient partials go to one slot per
+// (batch, work-group), so the final sums do not depend on timing.
+template <typename T, int N_LO, bool ADJ, bool PHASE>
+__global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
+  using C2 = cx<T>;
+  constexpr int LOGV = N_LO < 5 ? N_LO : 5;
+  constexpr int V = 1 << LOGV;
+  constexpr int U = 1 << N_LO;
+  constexpr int UPAD = U + (U >> 5);
+  constexpr int LOG_TA = N_LO - LOGV;
+  constexpr int TA = 1 << LOG_TA;
+  constexpr int NPF = 2;  // data-row values prefetched per thread
+  using CH = Chain<N_LO, LOGV>;
+  constexpr int NL = CH::count();
+  constexpr int LO0 = CH::lo(0);
+  constexpr uint32_t CB = sizeof(C2);
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int atom = tid >> LOG_TA;
+  const int tau = tid & (TA - 1);
+  const long long D = a.D;
+  const int G = gridDim.x;
+  const int hmask = (1 << a.n_hi) - 1;
+  const long long slot = a.slot_base + blockIdx.x;
+  const double Bd = (double)a.B;
+
+  // LDS: per atom a real and an imaginary plane of UPAD entries (transposes).  The
+  // |phi|^2 table [R][UPAD] and the sensitivity row g [UPAD] alias the first R+1 rows
+  // of the planes (2R rows in all); barriers separate their uses from the transposes.
+  T* planes = reinterpret_cast<T*>(smem);
+  T* re = planes + (size_t)atom * 2 * UPAD;
+  T* im = re + UPAD;
+  T* qb = planes;
+  T* gb = planes + (size_t)a.R * UPAD;
+  double* red = reinterpret_cast<double*>(smem + (((2 * (size_t)a.R * UPAD * sizeof(T)) + 15) & ~(size_t)15));
+
+  const T al = (T)a.alpha[atom];
+  const uint32_t vbytes = (uint32_t)(((long long)(a.R - 1) * D + U) * CB);
+  const uint32_t pos0 = (uint32_t)lay_pos<LOGV>(tau, 0, LO0);
+  const uint32_t vo0 = (uint32_t)(((long long)atom * D + pos0) * CB);
+  const bool row_data = a.grad_p != nullptr || a.loss_kind != 2;
+  double loss_acc = 0.0, h_acc = 0.0;
+
+  T px[V], py[V];
+  T pf[NPF];
+  auto issue = [&](int c) {
+    const int s = c >> a.n_hi;
+    const int h = c & hmask;
+    const C2* sbase = reinterpret_cast<const C2*>(a.src) + (long long)s * a.src_set_stride + ((long long)h << N_LO);
+    const rsrc_t rs = make_rsrc(sbase, vbytes);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      C2 t;
+      bload(t, rs, vo0, (uint32_t)(i << LO0) * CB);
+      px[i] = t.x;
+      py[i] = t.y;
+    }
+    if (row_data) {
+      const long long row = (long long)(a.b0 + s) * D + ((long long)h << N_LO);
+#pragma unroll
+      for (int k = 0; k < NPF; ++k) {
+        const int u = tid + k * nthr;
+        pf[k] = 0;
+        if (u < U) pf[k] = a.grad_p ? reinterpret_cast<const T*>(a.grad_p)[row + u] : (T)a.freqs[row + u];
+      }
+    }
+  };
+
+  int c = blockIdx.x;
+  if (c < a.nchunks) issue(c);
+  for (; c < a.nchunks; c += G) {
+    const int s = c >> a.n_hi;
+    const int h = c & hmask;
+    const int b = a.b0 + s;
+    const uint64_t pc = uniform_u64(a.pc[b]);
+    const T s2 = (T)ldexp(1.0, -nonz_count(pc, a.n));
+    T x[V], y[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      x[i] = px[i];
+      y[i] = py[i];
+    }
+    T fv[NPF];
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) fv[k] = pf[k];
+    if (c + G < a.nchunks) issue(c + G);
+
+    uint32_t ym = 0;
+    if constexpr (PHASE) {
+      ym = ymask_of(pc, a.n);
+      apply_phase<false, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
+    }
+    fwd_chain<0, CH, LOGV>(x, y, re, im, tau, pc);
+    // Final layout is lo = 0: alpha_r |phi_r|^2 into LDS, reduced over atoms per outcome.
+    T* qrow = qb + (size_t)atom * UPAD + pad_base<LOGV, 0>(tau);
+#pragma unroll
+    for (int i = 0; i < V; ++i) qrow[pad_off<0>(i)] = al * (x[i] * x[i] + y[i] * y[i]);
+    __syncthreads();
+    const long long row = (long long)b * D + ((long long)h << N_LO);
+    for (int k = 0, u = tid; u < U; ++k, u += nthr) {
+      T p = 0;
+      for (int r = 0; r < a.R; ++r) p += qb[(size_t)r * UPAD + pad32(u)];
+      p *= s2;
+      if (a.probs) reinterpret_cast<T*>(a.probs)[row + u] = p;
+      T d = 0;  // the data value of this outcome: dL/dp (generic) or the frequency
+      if (row_data) {
+        if (k < NPF) {
+#pragma unroll
+          for (int kk = 0; kk < NPF; ++kk)
+            if (kk == k) d = fv[kk];
+        } else {
+          d = a.grad_p ? reinterpret_cast<const T*>(a.grad_p)[row + u] : (T)a.freqs[row + u];
+        }
+      }
+      T g = 0;
+      if (a.grad_p) {
+        g = d;
+      } else if (a.loss_kind == 0) {
+        const double f = (double)d;
+        if (f > 0.0) {
+          const double piv = (double)p / Bd + a.eps;
+          loss_acc -= (f / Bd) * log(piv);
+          g = (T)(-(f / Bd) / piv / Bd);
+        }
+      } else if (a.loss_kind == 1) {
+        const double rr = ((double)p - (double)d) / Bd;
+        loss_acc += 0.5 * rr * rr;
+        g = (T)(rr / Bd);
+      }
+      if (a.gneg) reinterpret_cast<T*>(a.gneg)[row + u] = -g;
+      if (ADJ) gb[pad32(u)] = g * s2;
+    }
+    __syncthreads();
+    if (ADJ) {
+      T hl = 0;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const T gv = gb[pad_base<LOGV, 0>(tau) + pad_off<0>(i)];
+        hl += gv * (x[i] * x[i] + y[i] * y[i]);
+        const T sc = al * gv;
+        x[i] *= sc;
+        y[i] *= sc;
+      }
+      h_acc += (double)hl;
+      __syncthreads();  // every thread has read g before the planes are reused
+      adj_chain<NL - 1, CH, LOGV>(x, y, re, im, tau, pc);
+      if constexpr (PHASE) apply_phase<true, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
+      C2* dbase = reinterpret_cast<C2*>(a.dst) + (long long)s * a.R * D + ((long long)h << N_LO);
+      const rsrc_t rd = make_rsrc(dbase, vbytes);
+#pragma unroll
+      for (int i = 0; i < V; ++i) bstore(C2{x[i], y[i]}, rd, vo0, (uint32_t)(i << LO0) * CB);
+      __syncthreads();
+    }
+  }
+  if (a.part == nullptr) return;
+  if (ADJ) {
+    red[tid] = h_acc;
+    __syncthreads();
+    for (int st = TA >> 1; st > 0; st >>= 1) {
+      if (tau < st) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    if (tau == 0) a.part[(long long)(1 + atom) * a.nslots + slot] = red[tid];
+    __syncthreads();
+  }
+  if (a.grad_p == nullptr && a.loss_kind != 2) {
+    red[tid] = loss_acc;
+    __syncthreads();
+    int np2 = 1;
+    while (np2 < nthr) np2 <<= 1;
+    for (int st = np2 >> 1; st > 0; st >>= 1) {
+      if (tid < st && tid + st < nthr) red[tid] += red[tid + st];
+      __syncthreads();
+    }
+    if (tid == 0) a.part[slot] = red[0];
+  }
+}
+
+template <typename T, int N_LO, bool PHASE>
+hipError_t launch_lo_n(const Geometry& g, const LoArgs& a, bool adjoint, hipStream_t st) {
+  constexpr int LOGV = N_LO < 5 ? N_LO : 5;
+  const int nthr = g.R << (N_LO - LOGV);
+  const size_t lds = lo_lds_bytes(g);
+  const unsigned grid = (unsigned)g.grid_lo;
+  if (adjoint) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_stage_lo<T, N_LO, true, PHASE><<<grid, nthr, lds, st>>>(a);
+  } else {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, false, PHASE>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_stage_lo<T, N_LO, false, PHASE><<<grid, nthr, lds, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int N_LO, bool PHASE>
+int lo_occupancy_n(const Geometry& g) {
+  constexpr int LOGV = N_LO < 5 ? N_LO : 5;
+  const int nthr = g.R << (N_LO - LOGV);
+  const size_t lds = lo_lds_bytes(g);
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE>),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_stage_lo<T, N_LO, true, PHASE>, nthr, lds) !=
+      hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
+}
+
+// ------------------------------------------------------------------ stages A and C
+// Offset (elements from the tile origin) of tile position lam: tile bits below c
+// are columns (index bits 0..c-1), the rest are rows (index bits n_lo..).
+__device__ __forceinline__ uint32_t tile_off(uint32_t lam, int c, int n_lo) {
+  return ((lam >> c) << n_lo) | (lam & ((1u << c) - 1u));
+}
+
+// Mask of the register bits of layout `lo` that are tile rows (qubits of the
+// high pass) and are transformed in this layout: bits [max(lo, c), top).
+constexpr uint32_t rows_mask(int lo, int c, int top) {
+  uint32_t m = 0;
+  for (int k = 0; k < 5; ++k)
+    if (lo + k >= c && lo + k < top) m |= 1u << k;
+  return m;
+}
+
+template <int TB, int N_HI, bool ADJ>
+__global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
+  using T = float;
+  using C2 = float2;
+  constexpr int LOGV = 5;
+  constexpr int V = 1 << LOGV;
+  constexpr int C = TB - N_HI;           // column bits of the tile
+  constexpr int LO0 = TB - LOGV;
+  constexpr bool TWO = C < LO0;          // rows reach below the first layout
+  constexpr int LO1 = TB - 2 * LOGV > 0 ? TB - 2 * LOGV : 0;
+  constexpr int LOF = TWO ? LO1 : LO0;
+  constexpr uint32_t M0 = rows_mask(LO0, C, TB);
+  constexpr uint32_t M1 = rows_mask(LO1, C, LO0);
+  constexpr int NPAD = (1 << TB) + (1 << (TB - 5));
+  constexpr uint32_t CB = sizeof(C2);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* re = reinterpret_cast<T*>(smem);
+  T* im = re + NPAD;
+  const int tid = threadIdx.x;
+  const int n_lo = a.n_lo;
+  const int ncb = 1 << (n_lo - C);
+  const int r = blockIdx.x / ncb;
+  const int cb = blockIdx.x - r * ncb;
+  const long long D = a.D;
+  const uint32_t cbase = (uint32_t)cb << C;  // index of the tile origin within the atom
+  const long long origin = (long long)r * D + cbase;
+  const uint32_t vbytes = (uint32_t)((D - cbase) * CB);
+  const uint32_t t0 = tile_off(lay_pos<LOGV>(tid, 0, LO0), C, n_lo);
+  const uint32_t tf = tile_off(lay_pos<LOGV>(tid, 0, LOF), C, n_lo);
+  const uint32_t vo0 = t0 * CB;
+  const uint32_t vof = tf * CB;
+  auto off0 = [=](int i) { return tile_off((uint32_t)i << LO0, C, n_lo); };
+  auto offf = [=](int i) { return tile_off((uint32_t)i << LOF, C, n_lo); };
+
+  if (!ADJ) {
+    const rsrc_t rs = make_rsrc(reinterpret_cast<const C2*>(a.src) + origin, vbytes);
+    T kx[V], ky[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      C2 t;
+      bload(t, rs, vo0, off0(i) * CB);
+      kx[i] = t.x;
+      ky[i] = t.y;
+    }
+    for (int s = 0; s < a.S; ++s) {
+      const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
+      const uint32_t ym = ymask_of(pc, a.n);
+      T x[V], y[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        x[i] = kx[i];
+        y[i] = ky[i];
+      }
+      apply_phase<false, LOGV>(x, y, cbase | t0, ym, off0);
+      xform_xz<LOGV, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
+      if constexpr (TWO) {
+        lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
+        xform_xz<LOGV, M1>(x, y, layout_codes<LOGV>(pc, LO1, LO1, LO0, C, n_lo));
+      }
+      const rsrc_t rx = make_rsrc(reinterpret_cast<C2*>(a.dst) + (long long)s * a.R * D + origin, vbytes);
+#pragma unroll
+      for (int i = 0; i < V; ++i) bstore(C2{x[i], y[i]}, rx, vof, offf(i) * CB);
+    }
+  } else {
+    T ax[V], ay[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) ax[i] = ay[i] = T(0);
+    // The next setting's W tile is fetched while the current one is transformed.
+    T px[V], py[V];
+    auto issue = [&](int s) {
+      const rsrc_t rw = make_rsrc(reinterpret_cast<const C2*>(a.src) + (long long)s * a.R * D + origin, vbytes);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        C2 t;
+        bload(t, rw, vo0, off0(i) * CB);
+        px[i] = t.x;
+        py[i] = t.y;
+      }
+    };
+    if (a.S > 0) issue(0);
+    for (int s = 0; s < a.S; ++s) {
+      const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
+      const uint32_t ym = ymask_of(pc, a.n);
+      T x[V], y[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        x[i] = px[i];
+        y[i] = py[i];
+      }
+      if (s + 1 < a.S) issue(s + 1);
+      xform_xz<LOGV, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
+      if constexpr (TWO) {
+        lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
+        xform_xz<LOGV, M1>(x, y, layout_codes<LOGV>(pc, LO1, LO1, LO0, C, n_lo));
+      }
+      apply_phase<true, LOGV>(x, y, cbase | tf, ym, offf);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        ax[i] += x[i];
+        ay[i] += y[i];
+      }
+    }
+    const rsrc_t rg = make_rsrc(reinterpret_cast<C2*>(a.dst) + origin, vbytes);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      const uint32_t so = offf(i) * CB;
+      if (!a.first) {
+        C2 t;
+        bload(t, rg, vof, so);
+        ax[i] += t.x;
+        ay[i] += t.y;
+      }
+      bstore(C2{ax[i], ay[i]}, rg, vof, so);
+    }
+  }
+}
+
+template <int TB, int N_HI>
+hipError_t launch_hi_n(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st) {
+  const int nthr = 1 << (TB - 5);
+  const size_t lds = hi_lds_bytes(g);
+  const unsigned grid = (unsigned)(g.R << (g.n_lo - g.c));
+  if (adjoint) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, true>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_stage_hi<TB, N_HI, true><<<grid, nthr, lds, st>>>(a);
+  } else {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, false>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_stage_hi<TB, N_HI, false><<<grid, nthr, lds, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qst
