@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -164,12 +165,25 @@ void set_grid(qst_handle* h, Geometry& g, int S) {
   g.grid_lo = (int)std::max(1ll, std::min(chunks, resident));
 }
 
+// Settings per batch.  QST_SETTINGS_PER_BATCH (environment, read once) overrides
+// the default for tuning experiments.
+int env_batch() {
+  static const int v = [] {
+    const char* e = std::getenv("QST_SETTINGS_PER_BATCH");
+    return e ? std::max(0, std::atoi(e)) : 0;
+  }();
+  return v;
+}
+
 int default_S(const Geometry& g) {
+  if (env_batch() > 0) return std::min(env_batch(), g.B);
   const long long per = (long long)g.R * g.D * 2 * g.elem;
-  long long s = (2ll << 30) / std::max(per, 1ll);
+  long long s = (8ll << 30) / std::max(per, 1ll);
   if (s < 1) s = 1;
   if (s > g.B) s = g.B;
-  if (g.n_hi > 0 && s > 16) s = 16;  // enough to amortise the psi read and the gradient update
+  // X and W hold S settings each; 64 amortises the psi read and the gradient update
+  // (measured: 16 -> 267, 32 -> 251, 64 -> 243, 128 -> 241 ms at n=20, R=16, B=2000).
+  if (g.n_hi > 0 && s > 64) s = 64;
   return (int)s;
 }
 

@@ -219,29 +219,138 @@ __device__ __forceinline__ void xform_xz(T (&x)[1 << LOGV], T (&y)[1 << LOGV], u
   xform_xz_bit<0, LOGV, ACTIVE>(x, y, codes);
 }
 
-// Index-bit mask of the Y qubits of a decoded setting.
-__device__ __forceinline__ uint32_t ymask_of(uint64_t pc, int n) {
-  uint32_t m = 0;
-  for (int q = 0; q < n; ++q)
-    if (((pc >> (2 * q)) & 3ull) == 1ull) m |= 1u << q;
-  return __builtin_amdgcn_readfirstlane(m);
+// Orders the LDS accesses of a wavefront around an exchange between its lanes.
+// A wavefront's LDS operations execute in issue order; the fences keep the
+// compiler from reordering accesses across this point and emit no instruction.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// (x + i y) <- (x + i y) * (-i)^k  (forward)  or  * (+i)^k  (CONJ), k = kk & 3:
-//   (-i)^k: k=1 (y, -x), k=2 (-x, -y), k=3 (-y, x);  (+i)^k: k=1 (-y, x), k=3 (y, -x).
-// Odd k exchanges the components; the forward phase negates x' for k in {2,3}
-// and y' for k in {1,2}, the conjugate one the other way round.
-template <bool CONJ, typename T>
-__device__ __forceinline__ void rot_k(T& x, T& y, uint32_t kk) {
+// Index-bit mask of the Y qubits of a decoded setting: bit 2b of t marks code 1 at
+// index bit b, then the even bits are gathered into bits [0, 32) by halving steps.
+// Codes above the n qubits are zero (X), so n needs no special handling.
+__device__ __forceinline__ uint32_t ymask_of(uint64_t pc, int /*n*/) {
+  uint64_t t = pc & ~(pc >> 1) & 0x5555555555555555ull;
+  t = (t | (t >> 1)) & 0x3333333333333333ull;
+  t = (t | (t >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+  t = (t | (t >> 4)) & 0x00FF00FF00FF00FFull;
+  t = (t | (t >> 8)) & 0x0000FFFF0000FFFFull;
+  t = (t | (t >> 16)) & 0x00000000FFFFFFFFull;
+  return __builtin_amdgcn_readfirstlane((uint32_t)t);
+}
+
+// Y phase of one register layout.  Register i of a thread holds index base | off(i)
+// with off linear in the bits of i, so the exponent is k = mt + popcount(i & m5):
+// mt = popcount(base & ym) varies per lane, m5 marks the register bits whose index
+// bit belongs to a Y qubit.  Three lane masks describe k mod 4:
+//   sw = [k odd],  a = [k mod 4 in {2,3}],  b = [(k + 1) mod 4 in {2,3}].
+// The forward phase (-i)^k exchanges the components where k is odd and negates x'
+// where a, y' where b; the conjugate (+i)^k negates x' where b and y' where a.
+// Visiting the registers in Gray-code order changes popcount(i & m5) by at most one
+// per step; the masks then follow with a few scalar instructions:
+//   k -> k + 1 :  sw' = ~sw,  a' = b,  b' = ~a
+//   k -> k - 1 :  sw' = ~sw,  a' = ~b, b' = a
+struct PhaseMasks {
+  uint64_t sw, a, b;
+};
+
+__device__ __forceinline__ PhaseMasks phase_masks(uint32_t mt) {
+  PhaseMasks m;
+  m.sw = __builtin_amdgcn_ballot_w64((mt & 1u) != 0u);
+  m.a = __builtin_amdgcn_ballot_w64((mt & 2u) != 0u);
+  m.b = __builtin_amdgcn_ballot_w64(((mt + 1u) & 2u) != 0u);
+  return m;
+}
+
+// Phase of one register with the current masks (four v_cndmask, the negation as a
+// source modifier).
+template <bool CONJ>
+__device__ __forceinline__ void phase_apply(float& x, float& y, const PhaseMasks& m) {
+  float xs, ys, xo, yo;
+  const uint64_t nx = CONJ ? m.b : m.a;
+  const uint64_t ny = CONJ ? m.a : m.b;
+  asm("v_cndmask_b32_e64 %[xs], %[x], %[y], %[sw]\n\t"
+      "v_cndmask_b32_e64 %[ys], %[y], %[x], %[sw]\n\t"
+      "v_cndmask_b32_e64 %[xo], %[xs], -%[xs], %[nx]\n\t"
+      "v_cndmask_b32_e64 %[yo], %[ys], -%[ys], %[ny]"
+      : [xs] "=&v"(xs), [ys] "=&v"(ys), [xo] "=v"(xo), [yo] "=v"(yo)
+      : [x] "v"(x), [y] "v"(y), [sw] "s"(m.sw), [nx] "s"(nx), [ny] "s"(ny));
+  x = xo;
+  y = yo;
+}
+
+// One Gray-code step over register bit K (UP: the bit is being set) followed by the
+// phase of the register reached.  Scalar update and vector selects sit in one block
+// so that the masks of all registers are never live at once.
+template <int K, bool UP, bool CONJ>
+__device__ __forceinline__ void phase_step(float& x, float& y, PhaseMasks& m, uint64_t m5) {
+  uint64_t sw1, a1, b1, t;
+  float xs, ys, xo, yo;
+#define QST_PHASE_VALU(NX, NY)                                   \
+  "v_cndmask_b32_e64 %[xs], %[x], %[y], %[sw1]\n\t"            \
+  "v_cndmask_b32_e64 %[ys], %[y], %[x], %[sw1]\n\t"            \
+  "v_cndmask_b32_e64 %[xo], %[xs], -%[xs], %[" NX "]\n\t"      \
+  "v_cndmask_b32_e64 %[yo], %[ys], -%[ys], %[" NY "]"
+#define QST_PHASE_OPS                                                                          \
+  : [sw1] "=&s"(sw1), [a1] "=&s"(a1), [b1] "=&s"(b1), [t] "=&s"(t), [xs] "=&v"(xs), [ys] "=&v"(ys), \
+    [xo] "=v"(xo), [yo] "=v"(yo)                                                               \
+  : [x] "v"(x), [y] "v"(y), [sw] "s"(m.sw), [a] "s"(m.a), [b] "s"(m.b), [m5] "s"(m5), [k] "i"(K)  \
+  : "scc"
+#define QST_PHASE_UP                      \
+  "s_not_b64 %[t], %[a]\n\t"             \
+  "s_bitcmp1_b64 %[m5], %[k]\n\t"        \
+  "s_cselect_b64 %[a1], %[b], %[a]\n\t"  \
+  "s_cselect_b64 %[b1], %[t], %[b]\n\t"  \
+  "s_cselect_b64 %[t], -1, 0\n\t"        \
+  "s_xor_b64 %[sw1], %[sw], %[t]\n\t"
+#define QST_PHASE_DOWN                    \
+  "s_not_b64 %[t], %[b]\n\t"             \
+  "s_bitcmp1_b64 %[m5], %[k]\n\t"        \
+  "s_cselect_b64 %[a1], %[t], %[a]\n\t"  \
+  "s_cselect_b64 %[b1], %[a], %[b]\n\t"  \
+  "s_cselect_b64 %[t], -1, 0\n\t"        \
+  "s_xor_b64 %[sw1], %[sw], %[t]\n\t"
+  if constexpr (UP && !CONJ) asm(QST_PHASE_UP QST_PHASE_VALU("a1", "b1") QST_PHASE_OPS);
+  if constexpr (UP && CONJ) asm(QST_PHASE_UP QST_PHASE_VALU("b1", "a1") QST_PHASE_OPS);
+  if constexpr (!UP && !CONJ) asm(QST_PHASE_DOWN QST_PHASE_VALU("a1", "b1") QST_PHASE_OPS);
+  if constexpr (!UP && CONJ) asm(QST_PHASE_DOWN QST_PHASE_VALU("b1", "a1") QST_PHASE_OPS);
+#undef QST_PHASE_VALU
+#undef QST_PHASE_OPS
+#undef QST_PHASE_UP
+#undef QST_PHASE_DOWN
+  x = xo;
+  y = yo;
+  m.sw = sw1;
+  m.a = a1;
+  m.b = b1;
+}
+
+constexpr int gray(int j) { return j ^ (j >> 1); }
+constexpr int ctz_c(int j) { return (j & 1) ? 0 : 1 + ctz_c(j >> 1); }
+
+template <int J, int LOGV, bool CONJ>
+__device__ __forceinline__ void phase_walk(float (&x)[1 << LOGV], float (&y)[1 << LOGV], PhaseMasks& m,
+                                           uint64_t m5) {
+  if constexpr (J < (1 << LOGV)) {
+    constexpr int K = ctz_c(J);
+    constexpr int I = gray(J);
+    phase_step<K, ((I >> K) & 1) != 0, CONJ>(x[I], y[I], m, m5);
+    phase_walk<J + 1, LOGV, CONJ>(x, y, m, m5);
+  }
+}
+
+// FP64 form: exponent per element, k = mt + mi (mi uniform per register).
+template <bool CONJ>
+__device__ __forceinline__ void rot_k(double& x, double& y, uint32_t kk) {
   const bool sw = (kk & 1u) != 0u;
-  const T xs = sw ? y : x;
-  const T ys = sw ? x : y;
-  const bool n_a = (kk & 2u) != 0u;          // k in {2,3}
-  const bool n_b = ((kk + 1u) & 2u) != 0u;   // k in {1,2}
-  const bool nx = CONJ ? n_b : n_a;
-  const bool ny = CONJ ? n_a : n_b;
-  x = nx ? -xs : xs;
-  y = ny ? -ys : ys;
+  const double xs = sw ? y : x;
+  const double ys = sw ? x : y;
+  const bool n_a = (kk & 2u) != 0u;
+  const bool n_b = ((kk + 1u) & 2u) != 0u;
+  x = (CONJ ? n_b : n_a) ? -xs : xs;
+  y = (CONJ ? n_a : n_b) ? -ys : ys;
 }
 
 // Code word of the layout `lo` for the bits [from, to) of the block, where
@@ -300,6 +409,35 @@ __device__ __forceinline__ void bstore(const float2& v, rsrc_t rs, uint32_t voff
 }
 __device__ __forceinline__ void bstore(const double2& v, rsrc_t rs, uint32_t voff, uint32_t soff) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs, (int)voff, (int)soff, 0);
+}
+
+// Component forms: real and imaginary part in separate registers, the vector
+// assembled and split here (no aggregate temporaries in private memory).
+__device__ __forceinline__ void bload2(float& x, float& y, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0);
+  x = __uint_as_float(v.x);
+  y = __uint_as_float(v.y);
+}
+__device__ __forceinline__ void bload2(double& x, double& y, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 0);
+  x = __hiloint2double((int)v.y, (int)v.x);
+  y = __hiloint2double((int)v.w, (int)v.z);
+}
+__device__ __forceinline__ void bstore2(float x, float y, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  u32x2 v;
+  v.x = __float_as_uint(x);
+  v.y = __float_as_uint(y);
+  __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore2(double x, double y, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  const unsigned long long bx = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long by = (unsigned long long)__double_as_longlong(y);
+  u32x4 v;
+  v.x = (uint32_t)bx;
+  v.y = (uint32_t)(bx >> 32);
+  v.z = (uint32_t)by;
+  v.w = (uint32_t)(by >> 32);
+  __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)voff, (int)soff, 0);
 }
 
 // Layout chain of a block of 2^NB amplitudes with 2^LOGV registers per thread:

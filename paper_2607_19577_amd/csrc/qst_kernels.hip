@@ -52,15 +52,19 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ stage B
-// Low-stage LDS: per atom a real and an imaginary transpose plane of Upad
-// entries; the |phi|^2 table [R][Upad] and the sensitivity row [Upad] live in
-// the same space (they are never live together with a transpose); then one
-// double per thread for the reductions.
+// Low-stage LDS: the transpose planes, the |phi|^2 table [R][Upad] and the
+// sensitivity row [Upad] (layouts below), then one double per thread for the
+// reductions.
 size_t lo_lds_bytes(const Geometry& g) {
   const size_t U = (size_t)1 << g.n_lo;
   const size_t Upad = U + (U >> 5);
   const size_t nthr = (size_t)g.R << (g.n_lo - g.logv_lo);
-  const size_t planes = ((2 * (size_t)g.R * Upad * g.elem) + 15) & ~(size_t)15;
+  // Wavefront-local transposes (at most 64 threads per atom): one plane per atom
+  // plus a separate |phi|^2 table and g row; otherwise two planes per atom that
+  // the table and the g row alias.
+  const bool wave_local = g.n_lo - g.logv_lo <= 6;
+  const size_t rows = wave_local ? 2 * (size_t)g.R + 1 : 2 * (size_t)g.R;
+  const size_t planes = ((rows * Upad * g.elem) + 15) & ~(size_t)15;
   return planes + nthr * sizeof(double);
 }
 

@@ -48,6 +48,38 @@ __device__ __forceinline__ void lds_transpose(T (&x)[1 << LOGV], T (&y)[1 << LOG
   __syncthreads();
 }
 
+// The same transpose when all threads of an atom sit in one wavefront: one plane
+// takes the real and then the imaginary part.  LDS operations of a wavefront
+// complete in issue order, so only the compiler has to be kept from moving
+// them across the exchange points (wavefront-scope fences, no instructions).
+template <int LOGV, int LO_FROM, int LO_TO, typename T>
+__device__ __forceinline__ void lds_transpose_wave(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* pl, int tau) {
+  T* w = pl + pad_base<LOGV, LO_FROM>(tau);
+  const T* r = pl + pad_base<LOGV, LO_TO>(tau);
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) w[pad_off<LO_FROM>(i)] = x[i];
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) x[i] = r[pad_off<LO_TO>(i)];
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) w[pad_off<LO_FROM>(i)] = y[i];
+  wave_sync();
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) y[i] = r[pad_off<LO_TO>(i)];
+  wave_sync();
+}
+
+// Transpose of the low stage: wavefront-local (one plane per atom, re = that
+// plane) or work-group wide (separate re and im planes).
+template <bool WL, int LOGV, int LO_FROM, int LO_TO, typename T>
+__device__ __forceinline__ void lo_transpose(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau) {
+  if constexpr (WL)
+    lds_transpose_wave<LOGV, LO_FROM, LO_TO>(x, y, re, tau);
+  else
+    lds_transpose<LOGV, LO_FROM, LO_TO>(x, y, re, im, tau);
+}
+
 // Register bits of layout K of a chain that are new there (bits [lo(K), top(K))).
 template <typename CH, int K>
 constexpr uint32_t chain_mask() {
@@ -58,36 +90,46 @@ constexpr uint32_t chain_mask() {
 }
 
 // Butterflies of every layout of the chain, first to last.
-template <int K, typename CH, int LOGV, typename T>
+template <int K, typename CH, bool WL, int LOGV, typename T>
 __device__ __forceinline__ void fwd_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc) {
   if constexpr (K < CH::count()) {
-    if constexpr (K > 0) lds_transpose<LOGV, CH::lo(K - 1), CH::lo(K)>(x, y, re, im, tau);
+    if constexpr (K > 0) lo_transpose<WL, LOGV, CH::lo(K - 1), CH::lo(K)>(x, y, re, im, tau);
     xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
-    fwd_chain<K + 1, CH, LOGV>(x, y, re, im, tau, pc);
+    fwd_chain<K + 1, CH, WL, LOGV>(x, y, re, im, tau, pc);
   }
 }
 
 // The same butterflies from the last layout back to layout 0 (each is its own adjoint).
-template <int K, typename CH, int LOGV, typename T>
+template <int K, typename CH, bool WL, int LOGV, typename T>
 __device__ __forceinline__ void adj_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc) {
   xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
   if constexpr (K > 0) {
-    lds_transpose<LOGV, CH::lo(K), CH::lo(K - 1)>(x, y, re, im, tau);
-    adj_chain<K - 1, CH, LOGV>(x, y, re, im, tau, pc);
+    lo_transpose<WL, LOGV, CH::lo(K), CH::lo(K - 1)>(x, y, re, im, tau);
+    adj_chain<K - 1, CH, WL, LOGV>(x, y, re, im, tau, pc);
   }
 }
 
 // Apply the Y phase (or its conjugate) to the registers of one layout: register i
-// of this thread holds index base_index | off(i), with off(i) uniform, so the
-// exponent is popcount(base & ym) (per lane) + popcount(off(i) & ym) (uniform).
+// of this thread holds index base_index | off(i), off(i) uniform and linear in the
+// bits of i, so the exponent is popcount(base & ym) (per lane) + popcount(i & m5)
+// with m5 the register bits that land on Y qubits.
 template <bool CONJ, int LOGV, typename T, typename OffFn>
 __device__ __forceinline__ void apply_phase(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t base_index, uint32_t ym,
                                             OffFn off) {
   const uint32_t mt = (uint32_t)__popc(base_index & ym);
+  if constexpr (std::is_same<T, float>::value) {
+    uint32_t m5 = 0;
 #pragma unroll
-  for (int i = 0; i < (1 << LOGV); ++i) {
-    const uint32_t mi = __builtin_amdgcn_readfirstlane((uint32_t)__popc(off(i) & ym));
-    rot_k<CONJ>(x[i], y[i], mt + mi);
+    for (int k = 0; k < LOGV; ++k) m5 |= (off(1 << k) & ym) != 0u ? (1u << k) : 0u;
+    PhaseMasks m = phase_masks(mt);
+    phase_apply<CONJ>(x[0], y[0], m);
+    phase_walk<1, LOGV, CONJ>(x, y, m, (uint64_t)__builtin_amdgcn_readfirstlane(m5));
+  } else {
+#pragma unroll
+    for (int i = 0; i < (1 << LOGV); ++i) {
+      const uint32_t mi = __builtin_amdgcn_readfirstlane((uint32_t)__popc(off(i) & ym));
+      rot_k<CONJ>(x[i], y[i], mt + mi);
+    }
   }
 }
 
@@ -111,6 +153,7 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
   constexpr int NL = CH::count();
   constexpr int LO0 = CH::lo(0);
   constexpr uint32_t CB = sizeof(C2);
+  constexpr bool WL = LOG_TA <= 6;  // the threads of one atom form (part of) one wavefront
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
@@ -121,16 +164,20 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
   const int hmask = (1 << a.n_hi) - 1;
   const long long slot = a.slot_base + blockIdx.x;
   const double Bd = (double)a.B;
+  const float inv_b = (float)(1.0 / Bd);
+  const float eps_f = (float)a.eps;
 
-  // LDS: per atom a real and an imaginary plane of UPAD entries (transposes).  The
-  // |phi|^2 table [R][UPAD] and the sensitivity row g [UPAD] alias the first R+1 rows
-  // of the planes (2R rows in all); barriers separate their uses from the transposes.
+  // LDS, wavefront-local transposes (WL): one plane of UPAD entries per atom, then
+  // the table alpha_r |phi_r|^2 [R][UPAD] and the sensitivity row g [UPAD].
+  // Otherwise: a real and an imaginary plane per atom, with the table and g
+  // aliasing the first R+1 rows (barriers separate their uses from the transposes).
   T* planes = reinterpret_cast<T*>(smem);
-  T* re = planes + (size_t)atom * 2 * UPAD;
-  T* im = re + UPAD;
-  T* qb = planes;
-  T* gb = planes + (size_t)a.R * UPAD;
-  double* red = reinterpret_cast<double*>(smem + (((2 * (size_t)a.R * UPAD * sizeof(T)) + 15) & ~(size_t)15));
+  T* re = WL ? planes + (size_t)atom * UPAD : planes + (size_t)atom * 2 * UPAD;
+  T* im = WL ? re : re + UPAD;
+  T* qb = WL ? planes + (size_t)a.R * UPAD : planes;
+  T* gb = qb + (size_t)a.R * UPAD;
+  const size_t plane_rows = WL ? 2 * (size_t)a.R + 1 : 2 * (size_t)a.R;
+  double* red = reinterpret_cast<double*>(smem + (((plane_rows * UPAD * sizeof(T)) + 15) & ~(size_t)15));
 
   const T al = (T)a.alpha[atom];
   const uint32_t vbytes = (uint32_t)(((long long)(a.R - 1) * D + U) * CB);
@@ -139,56 +186,45 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
   const bool row_data = a.grad_p != nullptr || a.loss_kind != 2;
   double loss_acc = 0.0, h_acc = 0.0;
 
-  T px[V], py[V];
-  T pf[NPF];
-  auto issue = [&](int c) {
+  // Two register buffers take turns: chunk c + G is fetched into one while chunk c
+  // is transformed in place in the other.
+  T bpx[V], bpy[V], bpf[NPF], bqx[V], bqy[V], bqf[NPF];
+  auto issue = [&](int c, T (&bx)[V], T (&by)[V], T (&bf)[NPF]) __attribute__((always_inline)) {
     const int s = c >> a.n_hi;
     const int h = c & hmask;
     const C2* sbase = reinterpret_cast<const C2*>(a.src) + (long long)s * a.src_set_stride + ((long long)h << N_LO);
     const rsrc_t rs = make_rsrc(sbase, vbytes);
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      C2 t;
-      bload(t, rs, vo0, (uint32_t)(i << LO0) * CB);
-      px[i] = t.x;
-      py[i] = t.y;
+      bload2(bx[i], by[i], rs, vo0, (uint32_t)(i << LO0) * CB);
     }
     if (row_data) {
       const long long row = (long long)(a.b0 + s) * D + ((long long)h << N_LO);
 #pragma unroll
       for (int k = 0; k < NPF; ++k) {
         const int u = tid + k * nthr;
-        pf[k] = 0;
-        if (u < U) pf[k] = a.grad_p ? reinterpret_cast<const T*>(a.grad_p)[row + u] : (T)a.freqs[row + u];
+        bf[k] = 0;
+        if (u < U) bf[k] = a.grad_p ? reinterpret_cast<const T*>(a.grad_p)[row + u] : (T)a.freqs[row + u];
       }
     }
   };
 
-  int c = blockIdx.x;
-  if (c < a.nchunks) issue(c);
-  for (; c < a.nchunks; c += G) {
+  auto body = [&](int c, T (&x)[V], T (&y)[V], const T (&bf)[NPF]) __attribute__((always_inline)) {
     const int s = c >> a.n_hi;
     const int h = c & hmask;
     const int b = a.b0 + s;
     const uint64_t pc = uniform_u64(a.pc[b]);
     const T s2 = (T)ldexp(1.0, -nonz_count(pc, a.n));
-    T x[V], y[V];
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      x[i] = px[i];
-      y[i] = py[i];
-    }
     T fv[NPF];
 #pragma unroll
-    for (int k = 0; k < NPF; ++k) fv[k] = pf[k];
-    if (c + G < a.nchunks) issue(c + G);
+    for (int k = 0; k < NPF; ++k) fv[k] = bf[k];
 
     uint32_t ym = 0;
     if constexpr (PHASE) {
       ym = ymask_of(pc, a.n);
       apply_phase<false, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
     }
-    fwd_chain<0, CH, LOGV>(x, y, re, im, tau, pc);
+    fwd_chain<0, CH, WL, LOGV>(x, y, re, im, tau, pc);
     // Final layout is lo = 0: alpha_r |phi_r|^2 into LDS, reduced over atoms per outcome.
     T* qrow = qb + (size_t)atom * UPAD + pad_base<LOGV, 0>(tau);
 #pragma unroll
@@ -213,6 +249,21 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
       T g = 0;
       if (a.grad_p) {
         g = d;
+      } else if constexpr (std::is_same<T, float>::value) {
+        // FP32 path: p carries single-precision rounding already, so each term is
+        // formed in FP32 (hardware log2 and reciprocal, about 1 ulp) and summed in FP64.
+        if (a.loss_kind == 0) {
+          if (d > 0.0f) {
+            const float fb = d * inv_b;
+            const float piv = p * inv_b + eps_f;
+            loss_acc -= (double)(fb * (__builtin_amdgcn_logf(piv) * 0.693147180559945309f));
+            g = -(fb * inv_b) * __builtin_amdgcn_rcpf(piv);
+          }
+        } else if (a.loss_kind == 1) {
+          const float rr = (p - d) * inv_b;
+          loss_acc += (double)(0.5f * rr * rr);
+          g = rr * inv_b;
+        }
       } else if (a.loss_kind == 0) {
         const double f = (double)d;
         if (f > 0.0) {
@@ -240,14 +291,23 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
         y[i] *= sc;
       }
       h_acc += (double)hl;
-      __syncthreads();  // every thread has read g before the planes are reused
-      adj_chain<NL - 1, CH, LOGV>(x, y, re, im, tau, pc);
+      if constexpr (!WL) __syncthreads();  // every thread has read g before the planes are reused
+      adj_chain<NL - 1, CH, WL, LOGV>(x, y, re, im, tau, pc);
       if constexpr (PHASE) apply_phase<true, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
       C2* dbase = reinterpret_cast<C2*>(a.dst) + (long long)s * a.R * D + ((long long)h << N_LO);
       const rsrc_t rd = make_rsrc(dbase, vbytes);
 #pragma unroll
-      for (int i = 0; i < V; ++i) bstore(C2{x[i], y[i]}, rd, vo0, (uint32_t)(i << LO0) * CB);
-      __syncthreads();
+      for (int i = 0; i < V; ++i) bstore2(x[i], y[i], rd, vo0, (uint32_t)(i << LO0) * CB);
+      if constexpr (!WL) __syncthreads();
+    }
+  };
+  for (int c = blockIdx.x; c < a.nchunks; c += 2 * G) {
+    if (c == (int)blockIdx.x) issue(c, bpx, bpy, bpf);
+    if (c + G < a.nchunks) issue(c + G, bqx, bqy, bqf);
+    body(c, bpx, bpy, bpf);
+    if (c + G < a.nchunks) {
+      if (c + 2 * G < a.nchunks) issue(c + 2 * G, bpx, bpy, bpf);
+      body(c + G, bqx, bqy, bqf);
     }
   }
   if (a.part == nullptr) return;
@@ -361,10 +421,7 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
     T kx[V], ky[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      C2 t;
-      bload(t, rs, vo0, off0(i) * CB);
-      kx[i] = t.x;
-      ky[i] = t.y;
+      bload2(kx[i], ky[i], rs, vo0, off0(i) * CB);
     }
     for (int s = 0; s < a.S; ++s) {
       const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
@@ -383,35 +440,25 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
       }
       const rsrc_t rx = make_rsrc(reinterpret_cast<C2*>(a.dst) + (long long)s * a.R * D + origin, vbytes);
 #pragma unroll
-      for (int i = 0; i < V; ++i) bstore(C2{x[i], y[i]}, rx, vof, offf(i) * CB);
+      for (int i = 0; i < V; ++i) bstore2(x[i], y[i], rx, vof, offf(i) * CB);
     }
   } else {
     T ax[V], ay[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) ax[i] = ay[i] = T(0);
-    // The next setting's W tile is fetched while the current one is transformed.
-    T px[V], py[V];
-    auto issue = [&](int s) {
+    // Two register buffers take turns: the next setting's W tile is fetched into one
+    // while the other is transformed in place.
+    T px[V], py[V], qx[V], qy[V];
+    auto issue = [&](int s, T (&bx)[V], T (&by)[V]) __attribute__((always_inline)) {
       const rsrc_t rw = make_rsrc(reinterpret_cast<const C2*>(a.src) + (long long)s * a.R * D + origin, vbytes);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        C2 t;
-        bload(t, rw, vo0, off0(i) * CB);
-        px[i] = t.x;
-        py[i] = t.y;
+        bload2(bx[i], by[i], rw, vo0, off0(i) * CB);
       }
     };
-    if (a.S > 0) issue(0);
-    for (int s = 0; s < a.S; ++s) {
+    auto body = [&](int s, T (&x)[V], T (&y)[V]) __attribute__((always_inline)) {
       const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
       const uint32_t ym = ymask_of(pc, a.n);
-      T x[V], y[V];
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        x[i] = px[i];
-        y[i] = py[i];
-      }
-      if (s + 1 < a.S) issue(s + 1);
       xform_xz<LOGV, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
       if constexpr (TWO) {
         lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
@@ -423,18 +470,27 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         ax[i] += x[i];
         ay[i] += y[i];
       }
+    };
+    if (a.S > 0) issue(0, px, py);
+    for (int s = 0; s < a.S; s += 2) {
+      if (s + 1 < a.S) issue(s + 1, qx, qy);
+      body(s, px, py);
+      if (s + 1 < a.S) {
+        if (s + 2 < a.S) issue(s + 2, px, py);
+        body(s + 1, qx, qy);
+      }
     }
     const rsrc_t rg = make_rsrc(reinterpret_cast<C2*>(a.dst) + origin, vbytes);
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       const uint32_t so = offf(i) * CB;
       if (!a.first) {
-        C2 t;
-        bload(t, rg, vof, so);
-        ax[i] += t.x;
-        ay[i] += t.y;
+        T gx, gy;
+        bload2(gx, gy, rg, vof, so);
+        ax[i] += gx;
+        ay[i] += gy;
       }
-      bstore(C2{ax[i], ay[i]}, rg, vof, so);
+      bstore2(ax[i], ay[i], rg, vof, so);
     }
   }
 }
