@@ -26,11 +26,13 @@ struct qst_handle {
   std::string last_error;
   void* ws = nullptr;  // workspace arena (grow-only)
   size_t ws_bytes = 0;
+  std::vector<void*> retired;  // outgrown arenas, freed by qst_destroy (captured graphs may still use them)
   int* dflag = nullptr;  // device flag raised by kernels (bad Pauli code)
   int* hflag = nullptr;  // pinned host copy
   hipEvent_t flag_ev = nullptr;
   bool flag_pending = false;
   std::map<std::tuple<int, int, int, int>, int> tuned_S;  // (n, R, B, path) -> settings per batch
+  std::map<std::tuple<int, int, int, int>, int> occupancy;  // (n_lo, n_hi > 0, R, elem) -> low-stage WGs per CU
   // stage timing
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -59,9 +61,15 @@ hipEvent_t prof_event(qst_handle* h) {
   return h->ev_pool[h->ev_next++];
 }
 
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+  return cs != hipStreamCaptureStatusNone;
+}
+
 // Bracket the next launch(es) of one stage kind.
 void prof_begin(qst_handle* h, int kind) {
-  if (!h->prof) return;
+  if (!h->prof || capturing(h->stream)) return;
   hipEvent_t e = prof_event(h);
   if (!e) return;
   hipEventRecord(e, h->stream);
@@ -70,7 +78,7 @@ void prof_begin(qst_handle* h, int kind) {
 }
 
 void prof_end(qst_handle* h) {
-  if (!h->prof || h->open_kind < 0) return;
+  if (!h->prof || h->open_kind < 0 || capturing(h->stream)) return;
   hipEvent_t e = prof_event(h);
   if (!e) return;
   hipEventRecord(e, h->stream);
@@ -90,19 +98,13 @@ qst_status set_err(qst_handle* h, qst_status s, const std::string& msg) {
       return set_err(h, QST_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
   } while (0)
 
-bool capturing(hipStream_t st) {
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
-  return cs != hipStreamCaptureStatusNone;
-}
 
 qst_status ensure_ws(qst_handle* h, size_t bytes) {
   if (bytes <= h->ws_bytes) return QST_OK;
   if (capturing(h->stream))
     return set_err(h, QST_ERR_CAPTURE, "workspace must grow while the stream is capturing; call qst_plan first");
   if (h->ws) {
-    hipStreamSynchronize(h->stream);
-    hipFree(h->ws);
+    h->retired.push_back(h->ws);
     h->ws = nullptr;
     h->ws_bytes = 0;
   }
@@ -161,7 +163,14 @@ qst_status make_geometry(qst_handle* h, int n, int R, int B, int elem, Geometry&
 void set_grid(qst_handle* h, Geometry& g, int S) {
   g.S = S;
   const long long chunks = (long long)S << g.n_hi;
-  const long long resident = (long long)h->num_cu * (h->device >= 0 ? qst::lo_blocks_per_cu(g) : 1);
+  int per_cu = 1;
+  if (h->device >= 0) {
+    const auto key = std::make_tuple(g.n_lo, g.n_hi > 0 ? 1 : 0, g.R, g.elem);
+    auto it = h->occupancy.find(key);
+    if (it == h->occupancy.end()) it = h->occupancy.emplace(key, qst::lo_blocks_per_cu(g)).first;
+    per_cu = it->second;
+  }
+  const long long resident = (long long)h->num_cu * per_cu;
   g.grid_lo = (int)std::max(1ll, std::min(chunks, resident));
 }
 
@@ -224,7 +233,7 @@ WsLayout layout_ws(const Geometry& g, int S, qst_path path, bool with_gneg, size
 }
 
 qst_status check_flag(qst_handle* h) {
-  if (!h->flag_pending) return QST_OK;
+  if (!h->flag_pending || capturing(h->stream)) return QST_OK;
   if (hipEventQuery(h->flag_ev) != hipSuccess) return QST_OK;  // not reached yet: report later
   h->flag_pending = false;
   if (*h->hflag) {
@@ -572,6 +581,7 @@ qst_status qst_destroy(qst_handle* h) {
   hipSetDevice(h->device);
   hipStreamSynchronize(h->stream);
   if (h->ws) hipFree(h->ws);
+  for (void* p : h->retired) hipFree(p);
   if (h->dflag) hipFree(h->dflag);
   if (h->hflag) hipHostFree(h->hflag);
   if (h->flag_ev) hipEventDestroy(h->flag_ev);
@@ -616,17 +626,36 @@ qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_pat
     int S = default_S(g);
     if (h->device < 0) continue;
     if (autotune && path != QST_PATH_PLAIN_F32 && g.n_hi > 0) {
-      // Time the fused pass on a slice of the settings for each candidate batch size.
-      const int cands[] = {2, 4, 8, 16, 32};
-      const int B_try = std::min(g.B, 64);
+      // Time the fused pass on a slice of the settings for each candidate batch size
+      // (the same slice for every candidate, so the times compare directly).
+      const int cands[] = {8, 16, 32, 64, 128};
+      const int B_try = std::min(g.B, 256);
       qst_instance sub = inst[i];
       sub.n_settings = B_try;
       void* grad = nullptr;
       if (hipMalloc(&grad, (size_t)g.R * g.D * 2 * g.elem) != hipSuccess)
         return set_err(h, QST_ERR_OOM, "autotune scratch");
-      std::vector<double> wg_dummy;
       double* wg = nullptr;
-      hipMalloc(&wg, (size_t)g.R * 8 + 8);
+      if (hipMalloc(&wg, (size_t)g.R * 8 + 8) != hipSuccess) {
+        hipFree(grad);
+        return set_err(h, QST_ERR_OOM, "autotune scratch");
+      }
+      {
+        // One arena for the largest candidate, so the search does not leave outgrown ones behind.
+        size_t most = 0;
+        for (int cS : cands) {
+          if (cS > B_try || (size_t)cS * g.R * g.D * 2 * g.elem > (16ull << 30)) break;
+          Geometry gc = g;
+          set_grid(h, gc, cS);
+          most = std::max(most, layout_ws(gc, cS, path, false).total);
+        }
+        st = ensure_ws(h, most);
+        if (st != QST_OK) {
+          hipFree(grad);
+          hipFree(wg);
+          return st;
+        }
+      }
       float best = 1e30f;
       int best_S = S;
       hipEvent_t e0, e1;
@@ -634,7 +663,7 @@ qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_pat
       hipEventCreate(&e1);
       for (int cS : cands) {
         if (cS > B_try) break;
-        if ((size_t)cS * g.R * g.D * 2 * g.elem > (4ull << 30)) break;
+        if ((size_t)cS * g.R * g.D * 2 * g.elem > (16ull << 30)) break;  // X and W hold S settings each
         RunSpec rs{};
         rs.in = &sub;
         rs.path = path;
