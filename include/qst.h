@@ -37,8 +37,18 @@
  * (row-major, densely packed, complex numbers interleaved re,im).  The
  * library owns only the handle's workspace, which it allocates in
  * qst_plan (or on first use) and frees in qst_destroy; it never frees or
- * keeps caller memory beyond a call.  All calls are asynchronous on the
- * handle's stream; results are valid after the stream is synchronised.
+ * keeps caller memory beyond a call.  When a larger shape outgrows the
+ * workspace, a new one is allocated and the old one is kept until
+ * qst_destroy, so graphs captured earlier stay valid.  All calls are
+ * asynchronous on the handle's stream; results are valid after the stream
+ * is synchronised.
+ *
+ * Graph capture: qst_forward, qst_backward and qst_reweight_simplex may be
+ * captured once the workspace fits (qst_plan, or one eager call with the same
+ * shapes); they then enqueue kernels only (no allocation, no host sync, no
+ * memset nodes).  A captured graph reads the workspace, so graphs of one
+ * handle must not be replayed concurrently with each other or with eager
+ * calls on a different stream.
  *
  * Errors: every call returns a qst_status.  Arguments are validated before
  * anything is enqueued; on error nothing is enqueued and the handle's last
@@ -78,9 +88,7 @@ typedef enum {
   QST_PATH_AUTO = 0,          /* BUTTERFLY_F32                                        */
   QST_PATH_BUTTERFLY_F32 = 1, /* staged per-qubit butterflies, complex64 atoms, FP32   */
   QST_PATH_BUTTERFLY_F64 = 2, /* same kernels in FP64, complex128 atoms                */
-  QST_PATH_PLAIN_F32 = 3,     /* one HBM pass per qubit (reference kernel for speedups) */
-  QST_PATH_TILE_F16 = 4,      /* fused 4-qubit 16x16 tiles on FP16 MFMA, FP32 accumulate */
-  QST_PATH_TILE_BF16 = 5      /* same with BF16 MFMA operands                          */
+  QST_PATH_PLAIN_F32 = 3      /* one HBM pass per qubit (reference kernel for speedups) */
 } qst_path;
 
 /* One independent tomography instance (the arguments of the paper's problem
@@ -187,7 +195,8 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
  *   epilogues, 5 other (reweight, refactor helpers, reference path).
  * qst_profile_read synchronises the stream and returns, for one kind, the number of
  * launches and their summed event-to-event milliseconds since the last reset
- * (reset != 0 clears every kind).  Enabling allocates events: not during capture. */
+ * (reset != 0 clears every kind).  Enabling allocates events; launches made while
+ * the stream is capturing are not bracketed. */
 qst_status qst_profile_enable(qst_handle* h, int enable);
 qst_status qst_profile_read(qst_handle* h, int kind, int64_t* launches, double* total_ms, int reset);
 

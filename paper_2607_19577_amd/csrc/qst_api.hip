@@ -119,7 +119,7 @@ qst_status ensure_ws(qst_handle* h, size_t bytes) {
 
 int elem_of(qst_path p) { return p == QST_PATH_BUTTERFLY_F64 ? 8 : 4; }
 
-bool path_valid(int p) { return p >= QST_PATH_AUTO && p <= QST_PATH_TILE_BF16; }
+bool path_valid(int p) { return p >= QST_PATH_AUTO && p <= QST_PATH_PLAIN_F32; }
 
 qst_path resolve(qst_path p) { return p == QST_PATH_AUTO ? QST_PATH_BUTTERFLY_F32 : p; }
 
@@ -254,8 +254,6 @@ void post_flag(qst_handle* h) {
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 qst_status validate_instance(qst_handle* h, const qst_instance& in, qst_path path, bool need_freqs) {
-  if (path == QST_PATH_TILE_F16 || path == QST_PATH_TILE_BF16)
-    return set_err(h, QST_ERR_UNSUPPORTED, "tile paths are not built into this library");
   if (in.n_qubits < 1 || in.n_qubits > 20)
     return set_err(h, QST_ERR_SHAPE, "n_qubits must be in 1..20 (got " + std::to_string(in.n_qubits) + ")");
   if (in.rank < 1 || in.rank > 16) return set_err(h, QST_ERR_SHAPE, "rank must be in 1..16");
@@ -352,8 +350,6 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
       prof_end(h);
       continue;
     }
-    const bool tile = path == QST_PATH_TILE_F16 || path == QST_PATH_TILE_BF16;
-    const bool bf16 = path == QST_PATH_TILE_BF16;
     if (g.n_hi > 0) {
       qst::HiArgs ha{};
       ha.src = in.atoms;
@@ -370,7 +366,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
       ha.S = Sb;
       ha.first = 0;
       prof_begin(h, PK_HI_FWD);
-      QST_HIP(tile ? qst::launch_tile_hi(g, ha, false, bf16, s) : qst::launch_stage_hi(g, ha, false, s));
+      QST_HIP(qst::launch_stage_hi(g, ha, false, s));
       prof_end(h);
       la.src = X;
       la.src_set_stride = (long long)g.R * g.D;
@@ -380,7 +376,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
     }
     la.dst = W;
     prof_begin(h, PK_LO);
-    QST_HIP(tile ? qst::launch_tile_lo(g, la, Sb, rs.adjoint, bf16, s) : qst::launch_stage_lo(g, la, Sb, rs.adjoint, s));
+    QST_HIP(qst::launch_stage_lo(g, la, Sb, rs.adjoint, s));
     prof_end(h);
     if (rs.adjoint) {
       if (g.n_hi > 0) {
@@ -399,7 +395,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
         hc.S = Sb;
         hc.first = b0 == 0;
         prof_begin(h, PK_HI_ADJ);
-        QST_HIP(tile ? qst::launch_tile_hi(g, hc, true, bf16, s) : qst::launch_stage_hi(g, hc, true, s));
+        QST_HIP(qst::launch_stage_hi(g, hc, true, s));
         prof_end(h);
       } else {
         prof_begin(h, PK_HI_ADJ);

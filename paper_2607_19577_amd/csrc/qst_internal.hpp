@@ -85,10 +85,6 @@ hipError_t launch_convert(const void* src, int src_c64, void* dst, int dst_c64, 
                           hipStream_t st);
 hipError_t launch_axpy_c(void* y, int y_c64, const void* x, int x_c64, long long n, double a, hipStream_t st);
 
-// MFMA tile path (fused 4-qubit 16x16 Kronecker tiles).
-hipError_t launch_tile_lo(const Geometry& g, const LoArgs& a, int S, bool adjoint, bool bf16, hipStream_t st);
-hipError_t launch_tile_hi(const Geometry& g, const HiArgs& a, bool adjoint, bool bf16, hipStream_t st);
-
 size_t lo_lds_bytes(const Geometry& g);
 int lo_blocks_per_cu(const Geometry& g);
 size_t hi_lds_bytes(const Geometry& g);
