@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip refactor / plain-path timings")
     ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--batch", type=int, default=0, help="settings per batch (0: library default)")
+    ap.add_argument("--batch", type=int, default=0, help="settings per batch (0: library default or --autotune)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only a 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -164,6 +164,10 @@ def main():
         n_sample = 2 if n >= 18 else min(B, 64 if n <= 12 else 8)
         cpu = cpu_baseline(atoms, w, s, B, shots, n_sample, seed + 7)
         print(f"[bench] cpu baseline: {cpu['value']:.3e} amplitudes/s ({cpu['sample']})", file=sys.stderr, flush=True)
+
+    if args.batch > 0:
+        # read once by the library when it is loaded
+        os.environ["QST_SETTINGS_PER_BATCH"] = str(args.batch)
 
     import torch
 
