@@ -123,6 +123,20 @@ bool path_valid(int p) { return p >= QST_PATH_AUTO && p <= QST_PATH_PLAIN_F32; }
 
 qst_path resolve(qst_path p) { return p == QST_PATH_AUTO ? QST_PATH_BUTTERFLY_F32 : p; }
 
+// Tile bits of stage A (which = 0) and stage C (which = 1): QST_TILE_BITS_FWD and
+// QST_TILE_BITS_ADJ (environment, read once) override the defaults for tuning.
+int env_tile_bits(int which) {
+  static const int v[2] = {[] {
+                             const char* e = std::getenv("QST_TILE_BITS_FWD");
+                             return e ? std::atoi(e) : 0;
+                           }(),
+                           [] {
+                             const char* e = std::getenv("QST_TILE_BITS_ADJ");
+                             return e ? std::atoi(e) : 0;
+                           }()};
+  return v[which];
+}
+
 // Geometry of the staged path for (n, R, B).
 qst_status make_geometry(qst_handle* h, int n, int R, int B, int elem, Geometry& g) {
   g = Geometry{};
@@ -148,13 +162,19 @@ qst_status make_geometry(qst_handle* h, int n, int R, int B, int elem, Geometry&
     if (elem != 4)
       return set_err(h, QST_ERR_UNSUPPORTED,
                      "the FP64 path holds the whole state on chip: needs R * 2^n <= 8192");
-    g.t = std::min(n, 14);
-    g.c = g.t - g.n_hi;
-    const bool ok = (g.t == 14 && g.n_hi <= 10) || (g.t == 13 && g.n_hi <= 3) || (g.t == 12 && g.n_hi <= 2) ||
-                    (g.t == 11 && g.n_hi == 1);
-    if (!ok || g.c < 0 || g.c > g.n_lo)
+    auto tile_ok = [&](int t) {
+      const int c = t - g.n_hi;
+      const bool shape = (t == 14 && g.n_hi <= 10) || (t == 13 && g.n_hi <= 3) || (t == 12 && g.n_hi <= 2) ||
+                         (t == 11 && g.n_hi == 1);
+      return shape && c >= 0 && c <= g.n_lo;
+    };
+    g.t = std::min(n, env_tile_bits(0) > 0 ? env_tile_bits(0) : 14);
+    g.t_adj = std::min(n, env_tile_bits(1) > 0 ? env_tile_bits(1) : 14);
+    if (!tile_ok(g.t) || !tile_ok(g.t_adj))
       return set_err(h, QST_ERR_UNSUPPORTED,
                      "n=" + std::to_string(n) + ", R=" + std::to_string(R) + " is outside the tile-stage shapes");
+    g.c = g.t - g.n_hi;
+    g.c_adj = g.t_adj - g.n_hi;
   }
   return QST_OK;
 }
@@ -376,7 +396,16 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
     }
     la.dst = W;
     prof_begin(h, PK_LO);
-    QST_HIP(qst::launch_stage_lo(g, la, Sb, rs.adjoint, s));
+    {
+      qst::LoBatch lb{};
+      lb.count = 1;
+      lb.total = la.nchunks;
+      lb.rmax = g.R;
+      lb.begin[0] = 0;
+      lb.begin[1] = la.nchunks;
+      lb.a[0] = la;
+      QST_HIP(qst::launch_stage_lo(g, lb, rs.adjoint, s));
+    }
     prof_end(h);
     if (rs.adjoint) {
       if (g.n_hi > 0) {
@@ -389,13 +418,16 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
         hc.n = g.n;
         hc.n_lo = g.n_lo;
         hc.n_hi = g.n_hi;
-        hc.t = g.t;
-        hc.c = g.c;
+        hc.t = g.t_adj;
+        hc.c = g.c_adj;
         hc.b0 = b0;
         hc.S = Sb;
         hc.first = b0 == 0;
         prof_begin(h, PK_HI_ADJ);
-        QST_HIP(qst::launch_stage_hi(g, hc, true, s));
+        Geometry gc = g;
+        gc.t = g.t_adj;
+        gc.c = g.c_adj;
+        QST_HIP(qst::launch_stage_hi(gc, hc, true, s));
         prof_end(h);
       } else {
         prof_begin(h, PK_HI_ADJ);
@@ -419,6 +451,210 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
     QST_HIP(qst::launch_tangent(g.elem, in.atoms, rs.atom_grad, g.R, g.D, reinterpret_cast<double*>(ws + L.tan), G1, s));
   }
   prof_end(h);
+  return QST_OK;
+}
+
+// ---------------------------------------------------------------- batches of small instances
+// A call with several instances runs those whose state is one low-stage chunk (no
+// high bits) and whose settings fit one batch as batches of up to kBatchMax
+// instances with equal n: one launch per step for the whole batch (decode, fused
+// low stage, sum over settings, reductions, tangent projection).
+bool batchable(const Geometry& g, qst_path path) {
+  return path != QST_PATH_PLAIN_F32 && g.n_hi == 0 && default_S(g) >= g.B;
+}
+
+struct BatchLayout {
+  Geometry g;  // largest rank of the batch; grid of the fused launch
+  std::vector<size_t> pc, W, part;
+  size_t total = 0;
+};
+
+qst_status batch_layout(qst_handle* h, const std::vector<const RunSpec*>& rs, bool adjoint, size_t base,
+                        BatchLayout& L) {
+  const int n = rs[0]->in->n_qubits;
+  const int elem = elem_of(rs[0]->path);
+  int rmax = 1;
+  long long total = 0;
+  for (const RunSpec* r : rs) {
+    rmax = std::max(rmax, (int)r->in->rank);
+    total += r->in->n_settings;
+  }
+  qst_status st = make_geometry(h, n, rmax, (int)std::min<long long>(total, 1 << 30), elem, L.g);
+  if (st != QST_OK) return st;
+  if (L.g.n_hi != 0) return set_err(h, QST_ERR_SHAPE, "batched instance does not fit one chunk");
+  set_grid(h, L.g, (int)std::min<long long>(total, 1 << 30));
+  size_t o = base;
+  L.pc.clear();
+  L.W.clear();
+  L.part.clear();
+  for (const RunSpec* r : rs) {
+    const qst_instance& in = *r->in;
+    const size_t D = (size_t)1 << n;
+    L.pc.push_back(o);
+    o = al256(o + (size_t)in.n_settings * 8);
+    L.W.push_back(o);
+    if (adjoint) o = al256(o + (size_t)in.n_settings * in.rank * D * 2 * elem);
+    L.part.push_back(o);
+    o = al256(o + (size_t)(in.rank + 1) * L.g.grid_lo * 8);
+  }
+  L.total = o;
+  return QST_OK;
+}
+
+qst_status run_batch(qst_handle* h, const std::vector<const RunSpec*>& rs) {
+  const RunSpec& r0 = *rs[0];
+  const bool adjoint = r0.adjoint;
+  const bool want_loss = r0.grad_p == nullptr && r0.loss_kind != QST_LOSS_NONE;
+  BatchLayout L;
+  qst_status st = batch_layout(h, rs, adjoint, 0, L);
+  if (st != QST_OK) return st;
+  st = ensure_ws(h, L.total);
+  if (st != QST_OK) return st;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(h->ws);
+  hipStream_t s = h->stream;
+  const int n = r0.in->n_qubits;
+  const long long D = 1ll << n;
+  const int count = (int)rs.size();
+
+  qst::DecodeBatch db{};
+  db.count = count;
+  db.N = n;
+  qst::LoBatch lb{};
+  lb.count = count;
+  lb.rmax = L.g.R;
+  qst::SumBatch sb{};
+  sb.count = count;
+  sb.elem = L.g.elem;
+  qst::RowBatch rb{};
+  rb.count = count;
+  rb.rmax = L.g.R;
+  rb.nslots = L.g.grid_lo;
+  qst::TanBatch tb{};
+  tb.count = count;
+  tb.rmax = L.g.R;
+  tb.elem = L.g.elem;
+  int chunks = 0;
+  long long elems = 0;
+  for (int k = 0; k < count; ++k) {
+    const RunSpec& r = *rs[k];
+    const qst_instance& in = *r.in;
+    uint64_t* pc = reinterpret_cast<uint64_t*>(ws + L.pc[k]);
+    double* part = reinterpret_cast<double*>(ws + L.part[k]);
+    db.begin[k] = chunks;
+    db.settings[k] = in.settings;
+    db.pc[k] = pc;
+    qst::LoArgs& la = lb.a[k];
+    la.src = in.atoms;
+    la.src_set_stride = 0;
+    la.dst = adjoint ? ws + L.W[k] : nullptr;
+    la.pc = pc;
+    la.alpha = in.weights;
+    la.freqs = in.freqs;
+    la.grad_p = r.grad_p;
+    la.probs = r.probs;
+    la.gneg = nullptr;
+    la.part = (want_loss || adjoint) ? part : nullptr;
+    la.nslots = L.g.grid_lo;
+    la.slot_base = 0;
+    la.nchunks = in.n_settings;
+    la.D = D;
+    la.R = in.rank;
+    la.n = n;
+    la.n_lo = n;
+    la.n_hi = 0;
+    la.log_ta = L.g.n_lo - L.g.logv_lo;
+    la.b0 = 0;
+    la.B = in.n_settings;
+    la.loss_kind = r.grad_p ? 2 : (int)r.loss_kind;
+    la.eps = r.eps;
+    lb.begin[k] = chunks;
+    sb.begin[k] = elems;
+    sb.W[k] = ws + L.W[k];
+    sb.grad[k] = r.atom_grad;
+    sb.RD[k] = (long long)in.rank * D;
+    sb.S[k] = in.n_settings;
+    rb.part[k] = part;
+    rb.R[k] = in.rank;
+    rb.loss[k] = want_loss ? r.loss : nullptr;
+    rb.wgrad[k] = adjoint ? r.weight_grad : nullptr;
+    tb.atoms[k] = in.atoms;
+    tb.grad[k] = r.atom_grad;
+    tb.R[k] = in.rank;
+    tb.D[k] = D;
+    chunks += in.n_settings;
+    elems += (long long)in.rank * D;
+  }
+  db.begin[count] = lb.begin[count] = chunks;
+  db.total = lb.total = chunks;
+  sb.begin[count] = elems;
+  sb.total = elems;
+
+  prof_begin(h, PK_DECODE);
+  QST_HIP(qst::launch_decode_batch(db, h->dflag, s));
+  prof_end(h);
+  prof_begin(h, PK_LO);
+  QST_HIP(qst::launch_stage_lo(L.g, lb, adjoint, s));
+  prof_end(h);
+  if (adjoint) {
+    prof_begin(h, PK_HI_ADJ);
+    QST_HIP(qst::launch_sum_batch(sb, s));
+    prof_end(h);
+  }
+  prof_begin(h, PK_REDUCE);
+  if (want_loss || adjoint) QST_HIP(qst::launch_rowsum_batch(rb, s));
+  if (adjoint && r0.project_tangent) QST_HIP(qst::launch_tangent_batch(tb, s));
+  prof_end(h);
+  return QST_OK;
+}
+
+// Runs the instances of one call: batches of small instances (equal n), the rest
+// one by one.  `need` (optional) receives the workspace the call uses instead.
+qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* need = nullptr) {
+  std::map<int, std::vector<const RunSpec*>> groups;
+  std::vector<const RunSpec*> single;
+  for (const RunSpec& r : specs) {
+    Geometry g;
+    qst_status st = make_geometry(h, r.in->n_qubits, r.in->rank, r.in->n_settings, elem_of(r.path), g);
+    if (st != QST_OK) return st;
+    if (specs.size() > 1 && batchable(g, r.path))
+      groups[r.in->n_qubits].push_back(&r);
+    else
+      single.push_back(&r);
+  }
+  for (auto& kv : groups) {
+    const std::vector<const RunSpec*>& v = kv.second;
+    for (size_t b0 = 0; b0 < v.size(); b0 += qst::kBatchMax) {
+      std::vector<const RunSpec*> part(v.begin() + b0, v.begin() + std::min(v.size(), b0 + qst::kBatchMax));
+      if (part.size() == 1) {
+        single.push_back(part[0]);
+        continue;
+      }
+      if (need) {
+        BatchLayout L;
+        qst_status st = batch_layout(h, part, part[0]->adjoint, 0, L);
+        if (st != QST_OK) return st;
+        *need = std::max(*need, L.total);
+        continue;
+      }
+      qst_status st = run_batch(h, part);
+      if (st != QST_OK) return st;
+    }
+  }
+  for (const RunSpec* r : single) {
+    if (need) {
+      Geometry g;
+      qst_status st = make_geometry(h, r->in->n_qubits, r->in->rank, r->in->n_settings, elem_of(r->path), g);
+      if (st != QST_OK) return st;
+      int S = default_S(g);
+      auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)r->path));
+      if (it != h->tuned_S.end()) S = std::min(it->second, g.B);
+      set_grid(h, g, S);
+      *need = std::max(*need, layout_ws(g, S, r->path, false).total);
+      continue;
+    }
+    qst_status st = run_instance(h, *r);
+    if (st != QST_OK) return st;
+  }
   return QST_OK;
 }
 
@@ -701,6 +937,17 @@ qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_pat
   }
   st = device_gate(h);
   if (st != QST_OK) return st;
+  {
+    // the same call with these instances: batches of small ones need their own layout
+    std::vector<RunSpec> specs(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+      specs[i].in = &inst[i];
+      specs[i].path = path;
+      specs[i].adjoint = true;
+    }
+    st = run_call(h, specs, &need);
+    if (st != QST_OK) return st;
+  }
   return ensure_ws(h, need);
 }
 
@@ -721,8 +968,9 @@ qst_status qst_forward(qst_handle* h, const qst_instance* inst, int n_inst, void
   }
   st = device_gate(h);
   if (st != QST_OK) return st;
+  std::vector<RunSpec> specs(n_inst);
   for (int i = 0; i < n_inst; ++i) {
-    RunSpec rs{};
+    RunSpec& rs = specs[i];
     rs.in = &inst[i];
     rs.path = path;
     rs.loss_kind = loss ? loss_kind : QST_LOSS_NONE;
@@ -730,9 +978,9 @@ qst_status qst_forward(qst_handle* h, const qst_instance* inst, int n_inst, void
     rs.probs = probs ? probs[i] : nullptr;
     rs.loss = loss ? loss + i : nullptr;
     rs.adjoint = false;
-    st = run_instance(h, rs);
-    if (st != QST_OK) return st;
   }
+  st = run_call(h, specs);
+  if (st != QST_OK) return st;
   post_flag(h);
   return QST_OK;
 }
@@ -764,8 +1012,9 @@ qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, con
   }
   st = device_gate(h);
   if (st != QST_OK) return st;
+  std::vector<RunSpec> specs(n_inst);
   for (int i = 0; i < n_inst; ++i) {
-    RunSpec rs{};
+    RunSpec& rs = specs[i];
     rs.in = &inst[i];
     rs.path = path;
     rs.loss_kind = loss_kind;
@@ -776,9 +1025,9 @@ qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, con
     rs.loss = loss ? loss + i : nullptr;
     rs.project_tangent = project_tangent;
     rs.adjoint = true;
-    st = run_instance(h, rs);
-    if (st != QST_OK) return st;
   }
+  st = run_call(h, specs);
+  if (st != QST_OK) return st;
   post_flag(h);
   return QST_OK;
 }

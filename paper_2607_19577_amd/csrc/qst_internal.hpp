@@ -18,6 +18,7 @@ struct Geometry {
   int n, R, B;
   long long D;
   int n_lo, n_hi, t, c;
+  int t_adj, c_adj;  // tile of the adjoint stage C (may differ from stage A's)
   int logv_lo;  // registers per thread in the low stage: 2^logv_lo
   int grid_lo;
   int S;
@@ -37,12 +38,25 @@ struct LoArgs {
   double* part;               // [(R+1)][nslots]: row 0 loss, rows 1..R weight gradient
   long long nslots;
   long long slot_base;        // first slot of this launch (batch index x grid)
-  int nchunks;                // chunks in this launch: settings of the batch x 2^n_hi
+  int nchunks;                // chunks of this instance: settings of the batch x 2^n_hi
   long long D;
   int R, n, n_lo, n_hi, log_ta, b0, B;
   int loss_kind;
   double eps;
 };
+
+// One launch of the low stage over several instances of the same low-bit count:
+// chunks [begin[k], begin[k+1]) belong to instance a[k]; rmax is the largest rank
+// (block size and LDS layout).  Passed by value, so a captured graph keeps it.
+constexpr int kBatchMax = 16;
+struct LoBatch {
+  int count;
+  int total;
+  int rmax;
+  int begin[kBatchMax + 1];
+  LoArgs a[kBatchMax];
+};
+static_assert(sizeof(LoBatch) <= 4096, "kernel argument block too large");
 
 struct HiArgs {
   const void* src;  // forward: atoms [R][D];   adjoint: W [S][R][D]
@@ -52,9 +66,53 @@ struct HiArgs {
   int R, n, n_lo, n_hi, t, c, b0, S, first;
 };
 
+// Batches of small instances (whole state in one low-stage chunk, all settings in
+// one batch): one launch per step for up to kBatchMax instances, arguments by value.
+struct DecodeBatch {
+  int count;
+  int total;
+  int N;
+  int begin[kBatchMax + 1];
+  const uint8_t* settings[kBatchMax];
+  uint64_t* pc[kBatchMax];
+};
+struct SumBatch {  // grad_k[e] = sum_s W_k[s][e], e < R_k D
+  int count;
+  int elem;
+  long long total;
+  long long begin[kBatchMax + 1];
+  const void* W[kBatchMax];
+  void* grad[kBatchMax];
+  long long RD[kBatchMax];
+  int S[kBatchMax];
+};
+struct RowBatch {  // fixed-order sums of the per-work-group partials
+  int count;
+  int rmax;
+  long long nslots;
+  const double* part[kBatchMax];
+  int R[kBatchMax];
+  double* loss[kBatchMax];   // null: no loss row
+  double* wgrad[kBatchMax];  // null: no weight-gradient rows
+};
+struct TanBatch {  // grad_k[r] -= psi_k[r] <psi_k[r], grad_k[r]>
+  int count;
+  int rmax;
+  int elem;
+  const void* atoms[kBatchMax];
+  void* grad[kBatchMax];
+  int R[kBatchMax];
+  long long D[kBatchMax];
+};
+hipError_t launch_decode_batch(const DecodeBatch& b, int* flag, hipStream_t st);
+hipError_t launch_sum_batch(const SumBatch& b, hipStream_t st);
+hipError_t launch_rowsum_batch(const RowBatch& b, hipStream_t st);
+hipError_t launch_tangent_batch(const TanBatch& b, hipStream_t st);
+
 // Launchers (return the HIP status of the launch).
 hipError_t launch_decode(const uint8_t* settings, int B, int N, uint64_t* pc, int* flag, hipStream_t st);
-hipError_t launch_stage_lo(const Geometry& g, const LoArgs& a, int S, bool adjoint, hipStream_t st);
+// g: geometry of the largest rank in the batch (LDS size, grid).
+hipError_t launch_stage_lo(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
 hipError_t launch_stage_hi(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_sum_settings(const Geometry& g, const void* W, int S, void* grad, int first, hipStream_t st);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);

@@ -69,13 +69,14 @@ size_t lo_lds_bytes(const Geometry& g) {
 }
 
 // ------------------------------------------------------------------ stage dispatch
-hipError_t launch_stage_lo_f32(const Geometry& g, const LoArgs& a, bool adjoint, hipStream_t st);
-hipError_t launch_stage_lo_f64(const Geometry& g, const LoArgs& a, bool adjoint, hipStream_t st);
+hipError_t launch_stage_lo_f32(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
+hipError_t launch_stage_lo_f64(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
 int lo_occupancy_f32(const Geometry& g);
 int lo_occupancy_f64(const Geometry& g);
 
-hipError_t launch_stage_lo(const Geometry& g, const LoArgs& a, int, bool adjoint, hipStream_t st) {
-  return g.elem == 4 ? launch_stage_lo_f32(g, a, adjoint, st) : launch_stage_lo_f64(g, a, adjoint, st);
+hipError_t launch_stage_lo(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
+  if (m.count < 1 || m.count > kBatchMax || m.rmax != g.R) return hipErrorInvalidValue;
+  return g.elem == 4 ? launch_stage_lo_f32(g, m, adjoint, st) : launch_stage_lo_f64(g, m, adjoint, st);
 }
 
 // Resident low-stage work-groups per compute unit (the persistent grid is this
@@ -258,6 +259,129 @@ hipError_t launch_tangent(int elem, const void* atoms, void* grad, int R, long l
     k_tan_apply<double><<<(unsigned)nb, 256, 0, st>>>(reinterpret_cast<const double2*>(atoms),
                                                       reinterpret_cast<double2*>(grad), R, D, dots);
   }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batches of small instances
+// Linear search for the instance of a global item index (count <= kBatchMax, uniform).
+template <typename I>
+__device__ __forceinline__ int batch_find(const I* begin, int count, I x) {
+  int k = 0;
+  while (k + 1 < count && x >= begin[k + 1]) ++k;
+  return k;
+}
+
+__global__ void k_decode_batch(const DecodeBatch b, int* __restrict__ flag) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= b.total) return;
+  const int k = batch_find(b.begin, b.count, t);
+  const int row = t - b.begin[k];
+  uint64_t v = 0;
+  int bad = 0;
+  for (int j = 0; j < b.N; ++j) {
+    uint32_t c = b.settings[k][(size_t)row * b.N + j];
+    if (c > 2u) {
+      bad = 1;
+      c = 2u;
+    }
+    v |= (uint64_t)c << (2 * (b.N - 1 - j));
+  }
+  b.pc[k][row] = v;
+  if (bad) atomicOr(flag, 1);
+}
+
+hipError_t launch_decode_batch(const DecodeBatch& b, int* flag, hipStream_t st) {
+  if (b.total < 1) return hipSuccess;
+  const int bs = 256;
+  k_decode_batch<<<(b.total + bs - 1) / bs, bs, 0, st>>>(b, flag);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_sum_batch(const SumBatch b) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < b.total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int k = batch_find(b.begin, b.count, t);
+    const long long e = t - b.begin[k];
+    const cx<T>* W = reinterpret_cast<const cx<T>*>(b.W[k]);
+    cx<T> acc{0, 0};
+    for (int s = 0; s < b.S[k]; ++s) {
+      const cx<T> w = W[(long long)s * b.RD[k] + e];
+      acc.x += w.x;
+      acc.y += w.y;
+    }
+    reinterpret_cast<cx<T>*>(b.grad[k])[e] = acc;
+  }
+}
+
+hipError_t launch_sum_batch(const SumBatch& b, hipStream_t st) {
+  if (b.total < 1) return hipSuccess;
+  const int bs = 256;
+  long long nb = (b.total + bs - 1) / bs;
+  if (nb > 8192) nb = 8192;
+  if (b.elem == 4)
+    k_sum_batch<float><<<(unsigned)nb, bs, 0, st>>>(b);
+  else
+    k_sum_batch<double><<<(unsigned)nb, bs, 0, st>>>(b);
+  return hipGetLastError();
+}
+
+// Work-group (k, row): row 0 is instance k's loss, rows 1..R_k its weight gradient.
+__global__ __launch_bounds__(256) void k_rowsum_batch(const RowBatch b) {
+  __shared__ double red[256];
+  const int k = blockIdx.x, row = blockIdx.y;
+  if (row > b.R[k]) return;
+  if (row == 0 && b.loss[k] == nullptr) return;
+  if (row > 0 && b.wgrad[k] == nullptr) return;
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < b.nslots; i += 256) acc += b.part[k][(long long)row * b.nslots + i];
+  const double r = block_tree(acc, red);
+  if (threadIdx.x == 0) {
+    if (row == 0)
+      *b.loss[k] = r;
+    else
+      b.wgrad[k][row - 1] = r;
+  }
+}
+
+hipError_t launch_rowsum_batch(const RowBatch& b, hipStream_t st) {
+  if (b.count < 1) return hipSuccess;
+  k_rowsum_batch<<<dim3(b.count, b.rmax + 1), 256, 0, st>>>(b);
+  return hipGetLastError();
+}
+
+// Work-group (k, r): the FP64 inner product <psi, grad> over D, then the projection.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tan_batch(const TanBatch b) {
+  __shared__ double red[256];
+  const int k = blockIdx.x, r = blockIdx.y;
+  if (r >= b.R[k]) return;
+  const long long D = b.D[k];
+  const cx<T>* psi = reinterpret_cast<const cx<T>*>(b.atoms[k]) + (long long)r * D;
+  cx<T>* grad = reinterpret_cast<cx<T>*>(b.grad[k]) + (long long)r * D;
+  double re = 0.0, im = 0.0;
+  for (long long i = threadIdx.x; i < D; i += 256) {
+    const cx<T> p = psi[i], g = grad[i];
+    re += (double)p.x * g.x + (double)p.y * g.y;  // conj(p) g
+    im += (double)p.x * g.y - (double)p.y * g.x;
+  }
+  const T dr = (T)block_tree(re, red);
+  const T di = (T)block_tree(im, red);
+  for (long long i = threadIdx.x; i < D; i += 256) {
+    const cx<T> p = psi[i];
+    cx<T> g = grad[i];
+    g.x -= p.x * dr - p.y * di;
+    g.y -= p.x * di + p.y * dr;
+    grad[i] = g;
+  }
+}
+
+hipError_t launch_tangent_batch(const TanBatch& b, hipStream_t st) {
+  if (b.count < 1) return hipSuccess;
+  if (b.elem == 4)
+    k_tan_batch<float><<<dim3(b.count, b.rmax), 256, 0, st>>>(b);
+  else
+    k_tan_batch<double><<<dim3(b.count, b.rmax), 256, 0, st>>>(b);
   return hipGetLastError();
 }
 

@@ -6,23 +6,23 @@ namespace qst {
 #define QST_LO_CASES(X)                                                                                      \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
 
-hipError_t launch_stage_lo_f32(const Geometry& g, const LoArgs& a, bool adjoint, hipStream_t st) {
+hipError_t launch_stage_lo_f32(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
   if (g.n_hi == 0) {  // the state is one chunk: this stage applies the Y phases itself
     switch (g.n_lo) {
 #define QST_P(N) \
-  case N: return launch_lo_n<float, N, true>(g, a, adjoint, st);
+  case N: return launch_lo_n<float, N, true>(g, m, adjoint, st);
       QST_LO_CASES(QST_P)
 #undef QST_P
     }
     return hipErrorInvalidValue;
   }
   switch (g.n_lo) {
-    case 9: return launch_lo_n<float, 9, false>(g, a, adjoint, st);
-    case 10: return launch_lo_n<float, 10, false>(g, a, adjoint, st);
-    case 11: return launch_lo_n<float, 11, false>(g, a, adjoint, st);
-    case 12: return launch_lo_n<float, 12, false>(g, a, adjoint, st);
-    case 13: return launch_lo_n<float, 13, false>(g, a, adjoint, st);
-    case 14: return launch_lo_n<float, 14, false>(g, a, adjoint, st);
+    case 9: return launch_lo_n<float, 9, false>(g, m, adjoint, st);
+    case 10: return launch_lo_n<float, 10, false>(g, m, adjoint, st);
+    case 11: return launch_lo_n<float, 11, false>(g, m, adjoint, st);
+    case 12: return launch_lo_n<float, 12, false>(g, m, adjoint, st);
+    case 13: return launch_lo_n<float, 13, false>(g, m, adjoint, st);
+    case 14: return launch_lo_n<float, 14, false>(g, m, adjoint, st);
   }
   return hipErrorInvalidValue;
 }

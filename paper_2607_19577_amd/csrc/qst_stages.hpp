@@ -140,7 +140,7 @@ __device__ __forceinline__ void apply_phase(T (&x)[1 << LOGV], T (&y)[1 << LOGV]
 // current one.  Its loss and weight-gradient partials go to one slot per
 // (batch, work-group), so the final sums do not depend on timing.
 template <typename T, int N_LO, bool ADJ, bool PHASE>
-__global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
+__global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
   using C2 = cx<T>;
   constexpr int LOGV = N_LO < 5 ? N_LO : 5;
   constexpr int V = 1 << LOGV;
@@ -159,65 +159,123 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
   const int nthr = blockDim.x;
   const int atom = tid >> LOG_TA;
   const int tau = tid & (TA - 1);
-  const long long D = a.D;
   const int G = gridDim.x;
-  const int hmask = (1 << a.n_hi) - 1;
-  const long long slot = a.slot_base + blockIdx.x;
-  const double Bd = (double)a.B;
-  const float inv_b = (float)(1.0 / Bd);
-  const float eps_f = (float)a.eps;
+  const int RM = m.rmax;
 
-  // LDS, wavefront-local transposes (WL): one plane of UPAD entries per atom, then
-  // the table alpha_r |phi_r|^2 [R][UPAD] and the sensitivity row g [UPAD].
-  // Otherwise: a real and an imaginary plane per atom, with the table and g
-  // aliasing the first R+1 rows (barriers separate their uses from the transposes).
+  // LDS (sized for the largest rank of the launch), wavefront-local transposes (WL):
+  // one plane of UPAD entries per atom, then the table alpha_r |phi_r|^2 [R][UPAD]
+  // and the sensitivity row g [UPAD].  Otherwise: a real and an imaginary plane per
+  // atom, with the table and g aliasing the first R+1 rows (barriers separate their
+  // uses from the transposes).
   T* planes = reinterpret_cast<T*>(smem);
   T* re = WL ? planes + (size_t)atom * UPAD : planes + (size_t)atom * 2 * UPAD;
   T* im = WL ? re : re + UPAD;
-  T* qb = WL ? planes + (size_t)a.R * UPAD : planes;
-  T* gb = qb + (size_t)a.R * UPAD;
-  const size_t plane_rows = WL ? 2 * (size_t)a.R + 1 : 2 * (size_t)a.R;
+  T* qb = WL ? planes + (size_t)RM * UPAD : planes;
+  T* gb = qb + (size_t)RM * UPAD;
+  const size_t plane_rows = WL ? 2 * (size_t)RM + 1 : 2 * (size_t)RM;
   double* red = reinterpret_cast<double*>(smem + (((plane_rows * UPAD * sizeof(T)) + 15) & ~(size_t)15));
 
-  const T al = (T)a.alpha[atom];
-  const uint32_t vbytes = (uint32_t)(((long long)(a.R - 1) * D + U) * CB);
   const uint32_t pos0 = (uint32_t)lay_pos<LOGV>(tau, 0, LO0);
-  const uint32_t vo0 = (uint32_t)(((long long)atom * D + pos0) * CB);
-  const bool row_data = a.grad_p != nullptr || a.loss_kind != 2;
+  // Instance of a chunk of the launch (the chunks of instance k are [begin[k], begin[k+1])).
+  auto inst_of = [&](int c) {
+    int k = 0;
+    while (k + 1 < m.count && c >= m.begin[k + 1]) ++k;
+    return k;
+  };
+  // Buffer extent of one chunk (all atoms of the instance) and this thread's offset.
+  auto extent = [&](const LoArgs& a) { return (uint32_t)(((long long)(a.R - 1) * a.D + U) * CB); };
+  auto voff = [&](const LoArgs& a) { return (uint32_t)(((long long)atom * a.D + pos0) * CB); };
+
   double loss_acc = 0.0, h_acc = 0.0;
+  int cur = -1;            // instance whose partials are being accumulated
+  uint32_t touched = 0u;   // instances this work-group wrote partials for
+
+  // Partials of instance k for this work-group: loss in row 0, h_r in rows 1..R.
+  auto flush = [&](int k) {
+    const LoArgs& a = m.a[k];
+    touched |= 1u << k;
+    const long long slot = a.slot_base + blockIdx.x;
+    if (a.part != nullptr) {
+      if (ADJ) {
+        red[tid] = h_acc;
+        __syncthreads();
+        for (int st = TA >> 1; st > 0; st >>= 1) {
+          if (tau < st) red[tid] += red[tid + st];
+          __syncthreads();
+        }
+        if (tau == 0 && atom < a.R) a.part[(long long)(1 + atom) * a.nslots + slot] = red[tid];
+        __syncthreads();
+      }
+      if (a.grad_p == nullptr && a.loss_kind != 2) {
+        red[tid] = loss_acc;
+        __syncthreads();
+        int np2 = 1;
+        while (np2 < nthr) np2 <<= 1;
+        for (int st = np2 >> 1; st > 0; st >>= 1) {
+          if (tid < st && tid + st < nthr) red[tid] += red[tid + st];
+          __syncthreads();
+        }
+        if (tid == 0) a.part[slot] = red[0];
+        __syncthreads();
+      }
+    }
+    loss_acc = 0.0;
+    h_acc = 0.0;
+  };
 
   // Two register buffers take turns: chunk c + G is fetched into one while chunk c
   // is transformed in place in the other.
   T bpx[V], bpy[V], bpf[NPF], bqx[V], bqy[V], bqf[NPF];
   auto issue = [&](int c, T (&bx)[V], T (&by)[V], T (&bf)[NPF]) __attribute__((always_inline)) {
-    const int s = c >> a.n_hi;
-    const int h = c & hmask;
+    const int k = inst_of(c);
+    const LoArgs& a = m.a[k];
+    const int cl = c - m.begin[k];
+    const int s = cl >> a.n_hi;
+    const int h = cl & ((1 << a.n_hi) - 1);
     const C2* sbase = reinterpret_cast<const C2*>(a.src) + (long long)s * a.src_set_stride + ((long long)h << N_LO);
-    const rsrc_t rs = make_rsrc(sbase, vbytes);
+    // threads of atoms beyond this instance's rank lie outside the extent: they read zeros
+    const rsrc_t rs = make_rsrc(sbase, extent(a));
+    const uint32_t vo0 = voff(a);
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-      bload2(bx[i], by[i], rs, vo0, (uint32_t)(i << LO0) * CB);
-    }
-    if (row_data) {
-      const long long row = (long long)(a.b0 + s) * D + ((long long)h << N_LO);
+    for (int i = 0; i < V; ++i) bload2(bx[i], by[i], rs, vo0, (uint32_t)(i << LO0) * CB);
+    if (a.grad_p != nullptr || a.loss_kind != 2) {
+      const long long row = (long long)(a.b0 + s) * a.D + ((long long)h << N_LO);
 #pragma unroll
-      for (int k = 0; k < NPF; ++k) {
-        const int u = tid + k * nthr;
-        bf[k] = 0;
-        if (u < U) bf[k] = a.grad_p ? reinterpret_cast<const T*>(a.grad_p)[row + u] : (T)a.freqs[row + u];
+      for (int j = 0; j < NPF; ++j) {
+        const int u = tid + j * nthr;
+        bf[j] = 0;
+        if (u < U) bf[j] = a.grad_p ? reinterpret_cast<const T*>(a.grad_p)[row + u] : (T)a.freqs[row + u];
       }
     }
   };
 
+  // The body is inlined once per register buffer; every multiply-add in it is an
+  // explicit fma and implicit contraction is off, so both copies round alike and a
+  // chunk's results do not depend on which buffer (or which work-group) takes it.
   auto body = [&](int c, T (&x)[V], T (&y)[V], const T (&bf)[NPF]) __attribute__((always_inline)) {
-    const int s = c >> a.n_hi;
-    const int h = c & hmask;
+#pragma clang fp contract(off)
+    const int k = inst_of(c);
+    if (k != cur) {
+      if (cur >= 0) flush(cur);
+      cur = k;
+    }
+    const LoArgs& a = m.a[k];
+    const int cl = c - m.begin[k];
+    const int s = cl >> a.n_hi;
+    const int h = cl & ((1 << a.n_hi) - 1);
     const int b = a.b0 + s;
+    const long long D = a.D;
+    const bool active = atom < a.R;
+    const T al = active ? (T)a.alpha[atom] : T(0);
     const uint64_t pc = uniform_u64(a.pc[b]);
     const T s2 = (T)ldexp(1.0, -nonz_count(pc, a.n));
+    const double Bd = (double)a.B;
+    const float inv_b = (float)(1.0 / Bd);
+    const float eps_f = (float)a.eps;
+    const bool row_data = a.grad_p != nullptr || a.loss_kind != 2;
     T fv[NPF];
 #pragma unroll
-    for (int k = 0; k < NPF; ++k) fv[k] = bf[k];
+    for (int j = 0; j < NPF; ++j) fv[j] = bf[j];
 
     uint32_t ym = 0;
     if constexpr (PHASE) {
@@ -228,20 +286,20 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
     // Final layout is lo = 0: alpha_r |phi_r|^2 into LDS, reduced over atoms per outcome.
     T* qrow = qb + (size_t)atom * UPAD + pad_base<LOGV, 0>(tau);
 #pragma unroll
-    for (int i = 0; i < V; ++i) qrow[pad_off<0>(i)] = al * (x[i] * x[i] + y[i] * y[i]);
+    for (int i = 0; i < V; ++i) qrow[pad_off<0>(i)] = al * fma(x[i], x[i], y[i] * y[i]);
     __syncthreads();
     const long long row = (long long)b * D + ((long long)h << N_LO);
-    for (int k = 0, u = tid; u < U; ++k, u += nthr) {
+    for (int j = 0, u = tid; u < U; ++j, u += nthr) {
       T p = 0;
       for (int r = 0; r < a.R; ++r) p += qb[(size_t)r * UPAD + pad32(u)];
       p *= s2;
       if (a.probs) reinterpret_cast<T*>(a.probs)[row + u] = p;
       T d = 0;  // the data value of this outcome: dL/dp (generic) or the frequency
       if (row_data) {
-        if (k < NPF) {
+        if (j < NPF) {
 #pragma unroll
-          for (int kk = 0; kk < NPF; ++kk)
-            if (kk == k) d = fv[kk];
+          for (int jj = 0; jj < NPF; ++jj)
+            if (jj == j) d = fv[jj];
         } else {
           d = a.grad_p ? reinterpret_cast<const T*>(a.grad_p)[row + u] : (T)a.freqs[row + u];
         }
@@ -255,7 +313,7 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
         if (a.loss_kind == 0) {
           if (d > 0.0f) {
             const float fb = d * inv_b;
-            const float piv = p * inv_b + eps_f;
+            const float piv = fmaf(p, inv_b, eps_f);
             loss_acc -= (double)(fb * (__builtin_amdgcn_logf(piv) * 0.693147180559945309f));
             g = -(fb * inv_b) * __builtin_amdgcn_rcpf(piv);
           }
@@ -285,7 +343,7 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         const T gv = gb[pad_base<LOGV, 0>(tau) + pad_off<0>(i)];
-        hl += gv * (x[i] * x[i] + y[i] * y[i]);
+        hl = fma(gv, fma(x[i], x[i], y[i] * y[i]), hl);
         const T sc = al * gv;
         x[i] *= sc;
         y[i] *= sc;
@@ -295,59 +353,48 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoArgs a) {
       adj_chain<NL - 1, CH, WL, LOGV>(x, y, re, im, tau, pc);
       if constexpr (PHASE) apply_phase<true, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
       C2* dbase = reinterpret_cast<C2*>(a.dst) + (long long)s * a.R * D + ((long long)h << N_LO);
-      const rsrc_t rd = make_rsrc(dbase, vbytes);
+      const rsrc_t rd = make_rsrc(dbase, extent(a));
+      const uint32_t vo0 = voff(a);
 #pragma unroll
       for (int i = 0; i < V; ++i) bstore2(x[i], y[i], rd, vo0, (uint32_t)(i << LO0) * CB);
       if constexpr (!WL) __syncthreads();
     }
   };
-  for (int c = blockIdx.x; c < a.nchunks; c += 2 * G) {
+  for (int c = blockIdx.x; c < m.total; c += 2 * G) {
     if (c == (int)blockIdx.x) issue(c, bpx, bpy, bpf);
-    if (c + G < a.nchunks) issue(c + G, bqx, bqy, bqf);
+    if (c + G < m.total) issue(c + G, bqx, bqy, bqf);
     body(c, bpx, bpy, bpf);
-    if (c + G < a.nchunks) {
-      if (c + 2 * G < a.nchunks) issue(c + 2 * G, bpx, bpy, bpf);
+    if (c + G < m.total) {
+      if (c + 2 * G < m.total) issue(c + 2 * G, bpx, bpy, bpf);
       body(c + G, bqx, bqy, bqf);
     }
   }
-  if (a.part == nullptr) return;
-  if (ADJ) {
-    red[tid] = h_acc;
-    __syncthreads();
-    for (int st = TA >> 1; st > 0; st >>= 1) {
-      if (tau < st) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    if (tau == 0) a.part[(long long)(1 + atom) * a.nslots + slot] = red[tid];
-    __syncthreads();
-  }
-  if (a.grad_p == nullptr && a.loss_kind != 2) {
-    red[tid] = loss_acc;
-    __syncthreads();
-    int np2 = 1;
-    while (np2 < nthr) np2 <<= 1;
-    for (int st = np2 >> 1; st > 0; st >>= 1) {
-      if (tid < st && tid + st < nthr) red[tid] += red[tid + st];
-      __syncthreads();
-    }
-    if (tid == 0) a.part[slot] = red[0];
+  if (cur >= 0) flush(cur);
+  // Instances this work-group had no chunk of: zero partials, so every slot is defined.
+  for (int k = 0; k < m.count; ++k) {
+    if ((touched >> k) & 1u) continue;
+    const LoArgs& a = m.a[k];
+    if (a.part == nullptr) continue;
+    const long long slot = a.slot_base + blockIdx.x;
+    if (ADJ && tau == 0 && atom < a.R) a.part[(long long)(1 + atom) * a.nslots + slot] = 0.0;
+    if (tid == 0 && a.grad_p == nullptr && a.loss_kind != 2) a.part[slot] = 0.0;
   }
 }
 
 template <typename T, int N_LO, bool PHASE>
-hipError_t launch_lo_n(const Geometry& g, const LoArgs& a, bool adjoint, hipStream_t st) {
+hipError_t launch_lo_n(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
   constexpr int LOGV = N_LO < 5 ? N_LO : 5;
-  const int nthr = g.R << (N_LO - LOGV);
+  const int nthr = m.rmax << (N_LO - LOGV);
   const size_t lds = lo_lds_bytes(g);
   const unsigned grid = (unsigned)g.grid_lo;
   if (adjoint) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_lo<T, N_LO, true, PHASE><<<grid, nthr, lds, st>>>(a);
+    k_stage_lo<T, N_LO, true, PHASE><<<grid, nthr, lds, st>>>(m);
   } else {
     hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, false, PHASE>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_lo<T, N_LO, false, PHASE><<<grid, nthr, lds, st>>>(a);
+    k_stage_lo<T, N_LO, false, PHASE><<<grid, nthr, lds, st>>>(m);
   }
   return hipGetLastError();
 }
