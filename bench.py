@@ -122,6 +122,62 @@ def read_traffic(kernel_kind: str, workload: str):
     return float(d["bytes_per_launch"])
 
 
+def uneven_batch_extra(api, h, dev, seed: int, reps: int = 5):
+    """64 independent instances, n in 6..12, R in 1..8, B in 50..500 (fused CE backward with the
+    tangent projection): one call (batched launches), the same call replayed from a graph, and
+    64 one-instance calls.  Median wall time of `reps` runs each."""
+    import torch
+
+    rng = synth.make_rng(seed)
+    insts = []
+    amps = 0
+    for k, sh in enumerate(synth.uneven_batch_shapes(rng, 64)):
+        n, R, B = sh["n"], sh["R"], sh["B"]
+        r = synth.make_rng(seed + 1000 + k)
+        atoms = torch.from_numpy(synth.haar_atoms(r, R, 1 << n, dtype=np.complex64)).to(dev)
+        w = torch.from_numpy(synth.dirichlet_weights(r, R)).to(dev)
+        st = torch.from_numpy(synth.random_settings(r, B, n)).to(dev)
+        f = synth.porter_thomas_freqs_torch(seed + 2000 + k, B, 1 << n, synth.dirichlet_weights(r, min(R, 4)),
+                                            10_000, dev)
+        insts.append(api.Instance(atoms, w, st, f))
+        amps += B * R * (1 << n)
+    api.qst_plan(h, insts)
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts[1:])) * 1e3
+
+    one = lambda: api.qst_backward(h, insts, loss=api.LOSS_CE, eps=1e-8, project_tangent=True)  # noqa: E731
+    sep = lambda: [api.qst_backward(h, [i], loss=api.LOSS_CE, eps=1e-8, project_tangent=True)  # noqa: E731
+                   for i in insts]
+    batched_ms = timed(one)
+    separate_ms = timed(sep)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        h.set_stream(side)
+        one()
+    h.set_stream(torch.cuda.current_stream())
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        h.set_stream(torch.cuda.current_stream())
+        one()
+    h.set_stream(torch.cuda.current_stream())
+    graph_ms = timed(g.replay)
+    return {"instances": 64, "amplitudes": amps, "batched_call_ms": round(batched_ms, 3),
+            "separate_calls_ms": round(separate_ms, 3), "graph_replay_ms": round(graph_ms, 3),
+            "graph_amplitudes_per_s": amps / (graph_ms * 1e-3),
+            "speedup_graph_vs_separate": round(separate_ms / graph_ms, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +309,9 @@ def main():
         torch.cuda.synchronize()
         extras["refactor_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
         extras["refactor_R_out"] = int(res["R"][0])
+
+    if not args.no_extras:
+        extras["uneven64"] = uneven_batch_extra(api, h, dev, seed + 21)
 
     out = {
         "metric": "fwd+adjoint atom-setting amplitudes/s",

@@ -101,12 +101,15 @@ typedef enum {
  *   weights   [R] float64 (alpha)
  *   settings  [B][N] uint8 Pauli codes
  *   freqs     [B][D] float32 per-setting frequencies N_{b,u}/N_s; may be NULL when
- *             no loss is requested                                                 */
+ *             no loss is requested
+ *   settings_per_batch  0: library default (or the autotuned value); otherwise the
+ *             number of settings per batch of intermediate amplitudes (>= 1), which
+ *             also keeps the instance out of multi-instance batches            */
 typedef struct {
   int32_t n_qubits;
   int32_t rank;
   int32_t n_settings;
-  int32_t reserved;
+  int32_t settings_per_batch;
   const void* atoms;
   const double* weights;
   const uint8_t* settings;

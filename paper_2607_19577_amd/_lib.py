@@ -34,7 +34,7 @@ class QstInstance(ctypes.Structure):
         ("n_qubits", ctypes.c_int32),
         ("rank", ctypes.c_int32),
         ("n_settings", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("settings_per_batch", ctypes.c_int32),
         ("atoms", ctypes.c_void_p),
         ("weights", ctypes.c_void_p),
         ("settings", ctypes.c_void_p),

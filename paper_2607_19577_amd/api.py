@@ -96,6 +96,7 @@ class Instance:
     weights: torch.Tensor
     settings: torch.Tensor
     freqs: Optional[torch.Tensor] = None
+    settings_per_batch: int = 0  # 0: library default
 
     @property
     def shape(self):
@@ -118,7 +119,8 @@ class Instance:
             raise ValueError("atoms must be [R][2^N] and weights [R]")
         if self.freqs is not None and tuple(self.freqs.shape) != (B, 1 << N):
             raise ValueError("freqs must be [B][2^N]")
-        return QstInstance(N, R, B, 0, self.atoms.data_ptr(), self.weights.data_ptr(), self.settings.data_ptr(),
+        return QstInstance(N, R, B, int(self.settings_per_batch), self.atoms.data_ptr(), self.weights.data_ptr(),
+                           self.settings.data_ptr(),
                            None if self.freqs is None else self.freqs.data_ptr())
 
 

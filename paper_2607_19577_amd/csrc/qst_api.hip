@@ -179,9 +179,19 @@ qst_status make_geometry(qst_handle* h, int n, int R, int B, int elem, Geometry&
   return QST_OK;
 }
 
+// Work-groups per tile of the high-bit stages: enough (tile, split) pairs for two per
+// CU, each split with at least 8 settings of the batch.
+int split_of(const qst_handle* h, const Geometry& g, int c, int S) {
+  if (g.n_hi == 0) return 1;
+  const long long tiles = (long long)g.R << (g.n_lo - c);
+  const long long want = (2ll * h->num_cu + tiles - 1) / tiles;
+  return (int)std::max(1ll, std::min(want, (long long)std::max(1, S / 8)));
+}
+
 // Persistent low-stage grid for batches of S settings.
 void set_grid(qst_handle* h, Geometry& g, int S) {
   g.S = S;
+  g.split_adj = split_of(h, g, g.c_adj, S);
   const long long chunks = (long long)S << g.n_hi;
   int per_cu = 1;
   if (h->device >= 0) {
@@ -210,14 +220,14 @@ int default_S(const Geometry& g) {
   long long s = (8ll << 30) / std::max(per, 1ll);
   if (s < 1) s = 1;
   if (s > g.B) s = g.B;
-  // X and W hold S settings each; 64 amortises the psi read and the gradient update
-  // (measured: 16 -> 267, 32 -> 251, 64 -> 243, 128 -> 241 ms at n=20, R=16, B=2000).
-  if (g.n_hi > 0 && s > 64) s = 64;
+  // X and W hold S settings each (8 GiB each at most, S = 64 at n=20, R=16).  Larger
+  // batches amortise the psi read and the gradient update and need fewer launches
+  // (measured at n=20, R=16, B=2000: S = 16 -> 267, 32 -> 251, 64 -> 243 ms per step).
   return (int)s;
 }
 
 struct WsLayout {
-  size_t pc, X, W, part, lvl1, sums, tan, gneg, total;
+  size_t pc, X, W, part, lvl1, sums, tan, gneg, split, total;
 };
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -248,6 +258,8 @@ WsLayout layout_ws(const Geometry& g, int S, qst_path path, bool with_gneg, size
   o = al256(o + (size_t)g.R * G1 * 2 * 8 + (size_t)g.R * 2 * 8);
   L.gneg = o;
   if (with_gneg) o = al256(o + (size_t)g.B * g.D * g.elem);
+  L.split = o;
+  if (g.n_hi > 0 && g.split_adj > 1) o = al256(o + (size_t)g.split_adj * g.R * g.D * 2 * g.elem);
   L.total = o;
   return L;
 }
@@ -278,6 +290,7 @@ qst_status validate_instance(qst_handle* h, const qst_instance& in, qst_path pat
     return set_err(h, QST_ERR_SHAPE, "n_qubits must be in 1..20 (got " + std::to_string(in.n_qubits) + ")");
   if (in.rank < 1 || in.rank > 16) return set_err(h, QST_ERR_SHAPE, "rank must be in 1..16");
   if (in.n_settings < 1) return set_err(h, QST_ERR_SHAPE, "n_settings must be >= 1");
+  if (in.settings_per_batch < 0) return set_err(h, QST_ERR_SHAPE, "settings_per_batch must be >= 0");
   if (!in.atoms || !in.weights || !in.settings) return set_err(h, QST_ERR_INVALID_ARG, "null atoms/weights/settings");
   if (need_freqs && !in.freqs) return set_err(h, QST_ERR_INVALID_ARG, "freqs required for the requested loss");
   const size_t ea = path == QST_PATH_BUTTERFLY_F64 ? 16 : 8;
@@ -310,9 +323,10 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   qst_status st = make_geometry(h, in.n_qubits, in.rank, in.n_settings, elem_of(path), g);
   if (st != QST_OK) return st;
   int S = rs.S_override > 0 ? std::min(rs.S_override, g.B) : default_S(g);
-  {
+  if (rs.S_override <= 0) {
     auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)path));
-    if (rs.S_override <= 0 && it != h->tuned_S.end()) S = std::min(it->second, g.B);
+    if (it != h->tuned_S.end()) S = std::min(it->second, g.B);
+    if (in.settings_per_batch > 0) S = std::min((int)in.settings_per_batch, g.B);
   }
   set_grid(h, g, S);
   const WsLayout L = layout_ws(g, S, path, false, ws_base);
@@ -385,6 +399,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
       ha.b0 = b0;
       ha.S = Sb;
       ha.first = 0;
+      ha.nsplit = split_of(h, g, g.c, Sb);
       prof_begin(h, PK_HI_FWD);
       QST_HIP(qst::launch_stage_hi(g, ha, false, s));
       prof_end(h);
@@ -423,11 +438,15 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
         hc.b0 = b0;
         hc.S = Sb;
         hc.first = b0 == 0;
+        hc.nsplit = std::min(g.split_adj, split_of(h, g, g.c_adj, Sb));
+        hc.part = ws + L.split;
         prof_begin(h, PK_HI_ADJ);
         Geometry gc = g;
         gc.t = g.t_adj;
         gc.c = g.c_adj;
         QST_HIP(qst::launch_stage_hi(gc, hc, true, s));
+        if (hc.nsplit > 1)
+          QST_HIP(qst::launch_sum_splits(g.elem, hc.part, hc.nsplit, (long long)g.R * g.D, rs.atom_grad, hc.first, s));
         prof_end(h);
       } else {
         prof_begin(h, PK_HI_ADJ);
@@ -616,7 +635,7 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
     Geometry g;
     qst_status st = make_geometry(h, r.in->n_qubits, r.in->rank, r.in->n_settings, elem_of(r.path), g);
     if (st != QST_OK) return st;
-    if (specs.size() > 1 && batchable(g, r.path))
+    if (specs.size() > 1 && batchable(g, r.path) && r.in->settings_per_batch <= 0)
       groups[r.in->n_qubits].push_back(&r);
     else
       single.push_back(&r);
@@ -648,6 +667,7 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
       int S = default_S(g);
       auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)r->path));
       if (it != h->tuned_S.end()) S = std::min(it->second, g.B);
+      if (r->in->settings_per_batch > 0) S = std::min((int)r->in->settings_per_batch, g.B);
       set_grid(h, g, S);
       *need = std::max(*need, layout_ws(g, S, r->path, false).total);
       continue;

@@ -7,7 +7,7 @@ namespace qst {
 // Supported (tile bits, high bits) pairs of the FP32 path: n in 11..20 with the
 // low-stage sizes chosen by the host (n_lo >= 10).
 hipError_t launch_stage_hi(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st) {
-  if (g.elem != 4) return hipErrorInvalidValue;
+  if (g.elem != 4 || a.nsplit < 1 || a.nsplit > a.S) return hipErrorInvalidValue;
 #define QST_HI(TBv, NHv) \
   if (g.t == TBv && g.n_hi == NHv) return launch_hi_n<TBv, NHv>(g, a, adjoint, st);
   QST_HI(14, 1) QST_HI(14, 2) QST_HI(14, 3) QST_HI(14, 4) QST_HI(14, 5)

@@ -23,6 +23,7 @@ struct Geometry {
   int grid_lo;
   int S;
   int elem;      // bytes per real (4 or 8)
+  int split_adj; // work-groups per adjoint tile at batch size S (partial-sum slices in the workspace)
 };
 
 struct LoArgs {
@@ -62,8 +63,10 @@ struct HiArgs {
   const void* src;  // forward: atoms [R][D];   adjoint: W [S][R][D]
   void* dst;        // forward: X [S][R][D];    adjoint: atom gradient [R][D]
   const uint64_t* pc;
+  void* part;       // adjoint with nsplit > 1: per-split sums [nsplit][R][D]
   long long D;
   int R, n, n_lo, n_hi, t, c, b0, S, first;
+  int nsplit;       // work-groups per tile, each over a contiguous share of the S settings
 };
 
 // Batches of small instances (whole state in one low-stage chunk, all settings in
@@ -106,6 +109,9 @@ struct TanBatch {  // grad_k[r] -= psi_k[r] <psi_k[r], grad_k[r]>
 };
 hipError_t launch_decode_batch(const DecodeBatch& b, int* flag, hipStream_t st);
 hipError_t launch_sum_batch(const SumBatch& b, hipStream_t st);
+// grad[e] (first: =, else +=) sum_{k < nsplit} part[k][e], e < RD, in order of k.
+hipError_t launch_sum_splits(int elem, const void* part, int nsplit, long long RD, void* grad, int first,
+                             hipStream_t st);
 hipError_t launch_rowsum_batch(const RowBatch& b, hipStream_t st);
 hipError_t launch_tangent_batch(const TanBatch& b, hipStream_t st);
 

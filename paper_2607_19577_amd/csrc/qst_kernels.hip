@@ -89,15 +89,33 @@ size_t hi_lds_bytes(const Geometry& g) {
 }
 
 // ------------------------------------------------------------------ sum over settings (no high bits)
+// sum_s W[s][e] with four interleaved partial sums (more loads in flight per thread),
+// combined in a fixed order; the single-instance and the batched kernels share it, so
+// both give the same bits.
+template <typename T>
+__device__ __forceinline__ cx<T> settings_sum(const cx<T>* __restrict__ W, int S, long long RD, long long e) {
+  cx<T> a[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  int s = 0;
+  for (; s + 4 <= S; s += 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const cx<T> w = W[(long long)(s + j) * RD + e];
+      a[j].x += w.x;
+      a[j].y += w.y;
+    }
+  }
+  for (int j = 0; s < S; ++s, ++j) {
+    const cx<T> w = W[(long long)s * RD + e];
+    a[j].x += w.x;
+    a[j].y += w.y;
+  }
+  return cx<T>{(a[0].x + a[1].x) + (a[2].x + a[3].x), (a[0].y + a[1].y) + (a[2].y + a[3].y)};
+}
+
 template <typename T>
 __global__ void k_sum_settings(const cx<T>* __restrict__ W, int S, long long RD, cx<T>* __restrict__ grad, int first) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < RD; e += (long long)gridDim.x * blockDim.x) {
-    cx<T> acc{0, 0};
-    for (int s = 0; s < S; ++s) {
-      const cx<T> w = W[(long long)s * RD + e];
-      acc.x += w.x;
-      acc.y += w.y;
-    }
+    const cx<T> acc = settings_sum<T>(W, S, RD, e);
     if (first) {
       grad[e] = acc;
     } else {
@@ -118,6 +136,34 @@ hipError_t launch_sum_settings(const Geometry& g, const void* W, int S, void* gr
   else
     k_sum_settings<double><<<(unsigned)nb, bs, 0, st>>>(reinterpret_cast<const double2*>(W), S, RD,
                                                          reinterpret_cast<double2*>(grad), first);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_sum_splits(const cx<T>* __restrict__ part, int nsplit, long long RD, cx<T>* __restrict__ grad,
+                             int first) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < RD; e += (long long)gridDim.x * blockDim.x) {
+    cx<T> acc = first ? cx<T>{0, 0} : grad[e];
+    for (int k = 0; k < nsplit; ++k) {
+      const cx<T> v = part[(long long)k * RD + e];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    grad[e] = acc;
+  }
+}
+
+hipError_t launch_sum_splits(int elem, const void* part, int nsplit, long long RD, void* grad, int first,
+                             hipStream_t st) {
+  const int bs = 256;
+  long long nb = (RD + bs - 1) / bs;
+  if (nb > 8192) nb = 8192;
+  if (elem == 4)
+    k_sum_splits<float><<<(unsigned)nb, bs, 0, st>>>(reinterpret_cast<const float2*>(part), nsplit, RD,
+                                                      reinterpret_cast<float2*>(grad), first);
+  else
+    k_sum_splits<double><<<(unsigned)nb, bs, 0, st>>>(reinterpret_cast<const double2*>(part), nsplit, RD,
+                                                       reinterpret_cast<double2*>(grad), first);
   return hipGetLastError();
 }
 
@@ -303,14 +349,7 @@ __global__ void k_sum_batch(const SumBatch b) {
        t += (long long)gridDim.x * blockDim.x) {
     const int k = batch_find(b.begin, b.count, t);
     const long long e = t - b.begin[k];
-    const cx<T>* W = reinterpret_cast<const cx<T>*>(b.W[k]);
-    cx<T> acc{0, 0};
-    for (int s = 0; s < b.S[k]; ++s) {
-      const cx<T> w = W[(long long)s * b.RD[k] + e];
-      acc.x += w.x;
-      acc.y += w.y;
-    }
-    reinterpret_cast<cx<T>*>(b.grad[k])[e] = acc;
+    reinterpret_cast<cx<T>*>(b.grad[k])[e] = settings_sum<T>(reinterpret_cast<const cx<T>*>(b.W[k]), b.S[k], b.RD[k], e);
   }
 }
 

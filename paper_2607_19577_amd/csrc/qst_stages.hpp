@@ -450,8 +450,13 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   const int tid = threadIdx.x;
   const int n_lo = a.n_lo;
   const int ncb = 1 << (n_lo - C);
-  const int r = blockIdx.x / ncb;
-  const int cb = blockIdx.x - r * ncb;
+  // work-group = (tile, split); a split takes settings [s_lo, s_hi) of the batch
+  const int sp = blockIdx.x % a.nsplit;
+  const int tile = blockIdx.x / a.nsplit;
+  const int r = tile / ncb;
+  const int cb = tile - r * ncb;
+  const int s_lo = (int)((long long)sp * a.S / a.nsplit);
+  const int s_hi = (int)((long long)(sp + 1) * a.S / a.nsplit);
   const long long D = a.D;
   const uint32_t cbase = (uint32_t)cb << C;  // index of the tile origin within the atom
   const long long origin = (long long)r * D + cbase;
@@ -470,7 +475,7 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
     for (int i = 0; i < V; ++i) {
       bload2(kx[i], ky[i], rs, vo0, off0(i) * CB);
     }
-    for (int s = 0; s < a.S; ++s) {
+    for (int s = s_lo; s < s_hi; ++s) {
       const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
       const uint32_t ym = ymask_of(pc, a.n);
       T x[V], y[V];
@@ -518,20 +523,23 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         ay[i] += y[i];
       }
     };
-    if (a.S > 0) issue(0, px, py);
-    for (int s = 0; s < a.S; s += 2) {
-      if (s + 1 < a.S) issue(s + 1, qx, qy);
+    if (s_lo < s_hi) issue(s_lo, px, py);
+    for (int s = s_lo; s < s_hi; s += 2) {
+      if (s + 1 < s_hi) issue(s + 1, qx, qy);
       body(s, px, py);
-      if (s + 1 < a.S) {
-        if (s + 2 < a.S) issue(s + 2, px, py);
+      if (s + 1 < s_hi) {
+        if (s + 2 < s_hi) issue(s + 2, px, py);
         body(s + 1, qx, qy);
       }
     }
-    const rsrc_t rg = make_rsrc(reinterpret_cast<C2*>(a.dst) + origin, vbytes);
+    // one split: accumulate into the gradient; several: this split's sum to its slice
+    const bool whole = a.nsplit == 1;
+    C2* out = whole ? reinterpret_cast<C2*>(a.dst) : reinterpret_cast<C2*>(a.part) + (long long)sp * a.R * D;
+    const rsrc_t rg = make_rsrc(out + origin, vbytes);
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       const uint32_t so = offf(i) * CB;
-      if (!a.first) {
+      if (whole && !a.first) {
         T gx, gy;
         bload2(gx, gy, rg, vof, so);
         ax[i] += gx;
@@ -546,7 +554,7 @@ template <int TB, int N_HI>
 hipError_t launch_hi_n(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st) {
   const int nthr = 1 << (TB - 5);
   const size_t lds = hi_lds_bytes(g);
-  const unsigned grid = (unsigned)(g.R << (g.n_lo - g.c));
+  const unsigned grid = (unsigned)((g.R << (g.n_lo - g.c)) * a.nsplit);
   if (adjoint) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, true>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -57,7 +57,9 @@ def test_validation_paths(lib):
         # valid arguments on a validation-only handle stop before any launch
         assert lib.qst_forward(h, one, 1, None, ctypes.c_void_p(0x5000), _lib.LOSS_CE, 1e-8, 0) == 4
         # shape errors
-        for bad in (_inst(n=0), _inst(n=21), _inst(R=0), _inst(R=17), _inst(B=0)):
+        neg = _inst()
+        neg.settings_per_batch = -1
+        for bad in (_inst(n=0), _inst(n=21), _inst(R=0), _inst(R=17), _inst(B=0), neg):
             arr = (_lib.QstInstance * 1)(bad)
             assert lib.qst_forward(h, arr, 1, None, None, _lib.LOSS_NONE, 0.0, 0) == 2
         # null pointers

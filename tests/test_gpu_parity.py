@@ -102,6 +102,26 @@ def test_shapes_fp64(h, n, R, B):
     _check(_run(h, case, api.LOSS_CE, api.PATH_BUTTERFLY_F64), ref, TOL64, f"f64 n={n} R={R} B={B}")
 
 
+@pytest.mark.parametrize("n,R,B,spb", [
+    (12, 3, 37, 5),    # whole state in one chunk, 8 batches (gradient accumulated over batches)
+    (15, 16, 11, 4),   # tile stages, batches of 4, 4, 3 (ragged)
+    (17, 3, 9, 2),     # n_lo = 12, five batches
+])
+def test_setting_batches(h, n, R, B, spb):
+    """Several setting batches at small sizes (settings_per_batch set on the instance)."""
+    from paper_2607_19577_amd import api
+
+    case = make_case(700 + n, n, R, B, shots=5000)
+    ref = oracle(case, born.LOSS_CE, 1e-8, tier="axis")
+    inst = to_device(case, DEV)
+    inst.settings_per_batch = spb
+    probs, _ = api.qst_forward(h, [inst], want_probs=True)
+    lt, ag, wg = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8)
+    torch.cuda.synchronize()
+    got = (float(lt[0]), probs[0].cpu().numpy(), ag[0].cpu().numpy(), wg[0].cpu().numpy())
+    _check(got, ref, TOL32, f"batches n={n} R={R} B={B} spb={spb}")
+
+
 def test_generic_sensitivity_and_tangent(h):
     """grad_p mode (autograd route) and the tangent-space projection."""
     from paper_2607_19577_amd import api
