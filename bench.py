@@ -303,6 +303,15 @@ def main():
         torch.cuda.synchronize()
         fused_ms = (time.perf_counter() - t0) * 1e3
         extras["speedup_vs_plain"] = round(plain_ms / fused_ms, 2)
+        # MFMA tile paths (one pass per 4-qubit group, FP16 / BF16 operands)
+        for name, pth in (("tile_f16", api.PATH_TILE_F16), ("tile_bf16", api.PATH_TILE_BF16)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=pth, out=[grad])
+            torch.cuda.synchronize()
+            tms = (time.perf_counter() - t0) * 1e3
+            extras[f"{name}_path_ms"] = round(tms, 1)
+            extras[f"{name}_speedup_vs_plain"] = round(plain_ms / tms, 2)
         v0 = torch.from_numpy(synth.haar_atoms(synth.make_rng(seed + 11), 1, D)[0]).to(dev)
         t0 = time.perf_counter()
         res = api.qst_refactor(h, inst, api.LOSS_CE, 1e-8, 0.5, 1e-3, 1e-3, 8, 30, v0)

@@ -88,7 +88,11 @@ typedef enum {
   QST_PATH_AUTO = 0,          /* BUTTERFLY_F32                                        */
   QST_PATH_BUTTERFLY_F32 = 1, /* staged per-qubit butterflies, complex64 atoms, FP32   */
   QST_PATH_BUTTERFLY_F64 = 2, /* same kernels in FP64, complex128 atoms                */
-  QST_PATH_PLAIN_F32 = 3      /* one HBM pass per qubit (reference kernel for speedups) */
+  QST_PATH_PLAIN_F32 = 3,     /* one HBM pass per qubit (reference kernel for speedups) */
+  QST_PATH_TILE_F16 = 4,      /* one HBM pass per 4-qubit group: 16x16 complex Kronecker
+                                 tiles on the matrix cores, FP16 operands (scaled per
+                                 16x16 block), FP32 accumulation; complex64 atoms        */
+  QST_PATH_TILE_BF16 = 5      /* the same with BF16 operands (high and low parts)         */
 } qst_path;
 
 /* One independent tomography instance (the arguments of the paper's problem

@@ -119,7 +119,13 @@ qst_status ensure_ws(qst_handle* h, size_t bytes) {
 
 int elem_of(qst_path p) { return p == QST_PATH_BUTTERFLY_F64 ? 8 : 4; }
 
-bool path_valid(int p) { return p >= QST_PATH_AUTO && p <= QST_PATH_PLAIN_F32; }
+bool path_valid(int p) { return p >= QST_PATH_AUTO && p <= QST_PATH_TILE_BF16; }
+
+// Paths that keep every (setting, atom) vector in HBM and make one pass per qubit
+// (plain) or per group of four qubits (MFMA tiles).
+bool pass_path(qst_path p) {
+  return p == QST_PATH_PLAIN_F32 || p == QST_PATH_TILE_F16 || p == QST_PATH_TILE_BF16;
+}
 
 qst_path resolve(qst_path p) { return p == QST_PATH_AUTO ? QST_PATH_BUTTERFLY_F32 : p; }
 
@@ -233,7 +239,7 @@ struct WsLayout {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 long long nslots_of(const Geometry& g, qst_path path) {
-  if (path == QST_PATH_PLAIN_F32) return (long long)g.B * ((g.D + 255) / 256);
+  if (pass_path(path)) return (long long)g.B * ((g.D + 255) / 256);
   const long long batches = (g.B + g.S - 1) / g.S;
   return batches * g.grid_lo;
 }
@@ -245,9 +251,9 @@ WsLayout layout_ws(const Geometry& g, int S, qst_path path, bool with_gneg, size
   L.pc = o;
   o = al256(o + (size_t)g.B * 8);
   L.X = o;
-  if (g.n_hi > 0 || path == QST_PATH_PLAIN_F32) o = al256(o + vec);
+  if (g.n_hi > 0 || pass_path(path)) o = al256(o + vec);
   L.W = o;
-  if (path != QST_PATH_PLAIN_F32) o = al256(o + vec);
+  if (!pass_path(path)) o = al256(o + vec);
   L.part = o;
   o = al256(o + (size_t)(g.R + 1) * nslots_of(g, path) * 8);
   L.lvl1 = o;
@@ -372,13 +378,27 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
     la.b0 = b0;
     la.slot_base = (long long)(b0 / S) * g.grid_lo;
     la.nchunks = Sb << g.n_hi;
-    if (path == QST_PATH_PLAIN_F32) {
+    if (pass_path(path)) {
+      // groups of four qubits on the matrix cores (states of at least 2^8 amplitudes),
+      // the remaining qubits one pass each
+      const bool tiles = path != QST_PATH_PLAIN_F32 && g.D >= 256;
+      const bool bf16 = path == QST_PATH_TILE_BF16;
+      auto transform = [&](bool adj) -> qst_status {
+        int bit = 0;
+        if (tiles)
+          for (; bit + 4 <= g.n; bit += 4)
+            QST_HIP(qst::launch_tile_pass(X, Sb, g.R, g.D, bit, pc, b0, adj, bf16, s));
+        for (; bit < g.n; ++bit) QST_HIP(qst::launch_plain_qubit(X, Sb, g.R, g.D, bit, pc, b0, adj, s));
+        return QST_OK;
+      };
       prof_begin(h, PK_OTHER);
       QST_HIP(qst::launch_plain_copy(in.atoms, X, Sb, g.R, g.D, s));
-      for (int bit = 0; bit < g.n; ++bit) QST_HIP(qst::launch_plain_qubit(X, Sb, g.R, g.D, bit, pc, b0, false, s));
+      st = transform(false);
+      if (st != QST_OK) return st;
       QST_HIP(qst::launch_plain_point(la, X, Sb, s));
       if (rs.adjoint) {
-        for (int bit = 0; bit < g.n; ++bit) QST_HIP(qst::launch_plain_qubit(X, Sb, g.R, g.D, bit, pc, b0, true, s));
+        st = transform(true);
+        if (st != QST_OK) return st;
         QST_HIP(qst::launch_plain_sum(X, Sb, g.R, g.D, rs.atom_grad, b0 == 0, s));
       }
       prof_end(h);
@@ -479,7 +499,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
 // instances with equal n: one launch per step for the whole batch (decode, fused
 // low stage, sum over settings, reductions, tangent projection).
 bool batchable(const Geometry& g, qst_path path) {
-  return path != QST_PATH_PLAIN_F32 && g.n_hi == 0 && default_S(g) >= g.B;
+  return !pass_path(path) && g.n_hi == 0 && default_S(g) >= g.B;
 }
 
 struct BatchLayout {
@@ -877,7 +897,7 @@ qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_pat
     if (st != QST_OK) return st;
     int S = default_S(g);
     if (h->device < 0) continue;
-    if (autotune && path != QST_PATH_PLAIN_F32 && g.n_hi > 0) {
+    if (autotune && !pass_path(path) && g.n_hi > 0) {
       // Time the fused pass on a slice of the settings for each candidate batch size
       // (the same slice for every candidate, so the times compare directly).
       const int cands[] = {8, 16, 32, 64, 128};

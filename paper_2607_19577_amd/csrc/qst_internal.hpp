@@ -140,6 +140,11 @@ hipError_t launch_plain_qubit(void* X, int S, int R, long long D, int bit, const
 hipError_t launch_plain_point(const LoArgs& a, void* X, int S, hipStream_t st);
 hipError_t launch_plain_sum(const void* X, int S, int R, long long D, void* grad, int first, hipStream_t st);
 
+// MFMA tile path: one pass over X [S][R][D] (complex64, in place) applying the
+// setting's 16x16 tile (adjoint: its conjugate transpose) on index bits [gb, gb+4).
+hipError_t launch_tile_pass(void* X, int S, int R, long long D, int gb, const uint64_t* pc, int b0, bool adj,
+                            bool bf16, hipStream_t st);
+
 // Vector helpers for the refactorisation (complex128 Krylov vectors).
 hipError_t launch_dots(const void* Q, int k, long long ldq, const void* w, int w_is_c64, long long D,
                        double* part, int g1, double* out_re_im, hipStream_t st);

@@ -1,0 +1,102 @@
+"""GPU parity of the MFMA tile paths (16x16 complex Kronecker tiles of four qubits,
+FP16 or BF16 operands, FP32 accumulation) against the FP64 oracle.
+
+Tolerance 1e-2 (norm-wise, and element-wise scaled by the largest reference element)
+for probabilities, loss, atom and weight gradients.  The BF16 path splits each
+amplitude into two BF16 parts and is checked at 1e-4 as well; the FP16 path scales
+each 16x16 block before rounding and is checked at 3e-3.  At the full n=20, R=16
+shape the tile paths are compared with the FP32 butterfly path on a setting subset.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import born
+from tests._cases import close, make_case, oracle, rel, to_device
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+TOL_TILE = 1e-2
+TIGHT = {"PATH_TILE_F16": 3e-3, "PATH_TILE_BF16": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def h():
+    from paper_2607_19577_amd import api
+
+    with api.Handle(0) as hd:
+        yield hd
+
+
+def _run(h, case, path, kind=born.LOSS_CE):
+    from paper_2607_19577_amd import api
+
+    inst = to_device(case, DEV)
+    probs, _ = api.qst_forward(h, [inst], want_probs=True, path=path)
+    lt, ag, wg = api.qst_backward(h, [inst], loss=kind, eps=1e-8, path=path)
+    torch.cuda.synchronize()
+    return float(lt[0]), probs[0].cpu().numpy(), ag[0].cpu().numpy(), wg[0].cpu().numpy()
+
+
+@pytest.mark.parametrize("path_name", ["PATH_TILE_F16", "PATH_TILE_BF16"])
+@pytest.mark.parametrize("n,R,B", [
+    (4, 2, 81),    # below 2^8 amplitudes: per-qubit passes only
+    (8, 2, 5),     # two tile groups
+    (10, 4, 20),   # two groups and two single qubits
+    (13, 3, 6),    # three groups and one single qubit
+    (16, 5, 3),    # four groups
+])
+def test_tile_path_matches_oracle(h, path_name, n, R, B):
+    from paper_2607_19577_amd import api
+
+    path = getattr(api, path_name)
+    case = make_case(900 + n, n, R, B, shots=5000, exhaustive=(n == 4))
+    L, p, ga, gw = _run(h, case, path)
+    Lr, pr, gar, gwr = oracle(case, born.LOSS_CE, 1e-8, tier="axis")
+    tol = TIGHT[path_name] if n >= 8 else 1e-5
+    assert abs(L - Lr) <= tol * abs(Lr), (L, Lr)
+    assert close(p, pr, tol), rel(p, pr)
+    for r in range(R):
+        assert close(ga[r], gar[r], tol), (r, rel(ga[r], gar[r]))
+    assert close(gw, gwr, tol), rel(gw, gwr)
+    assert tol <= TOL_TILE
+
+
+@pytest.mark.parametrize("path_name", ["PATH_TILE_F16", "PATH_TILE_BF16"])
+def test_tile_path_least_squares(h, path_name):
+    from paper_2607_19577_amd import api
+
+    case = make_case(950, 11, 3, 9, shots=5000)
+    L, p, ga, gw = _run(h, case, getattr(api, path_name), kind=born.LOSS_LS)
+    Lr, pr, gar, gwr = oracle(case, born.LOSS_LS, 1e-8, tier="axis")
+    tol = TIGHT[path_name]
+    assert abs(L - Lr) <= tol * abs(Lr), (L, Lr)
+    for r in range(3):
+        assert close(ga[r], gar[r], tol), (r, rel(ga[r], gar[r]))
+
+
+@pytest.mark.parametrize("path_name", ["PATH_TILE_F16", "PATH_TILE_BF16"])
+def test_tile_path_full_size_subset(h, path_name):
+    """n=20, R=16 on four settings: the tile path against the FP32 butterfly path."""
+    from paper_2607_19577_amd import api
+
+    rng = synth.make_rng(960)
+    n, R, B = 20, 16, 4
+    atoms = torch.from_numpy(synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64)).to(DEV)
+    w = torch.from_numpy(synth.dirichlet_weights(rng, R)).to(DEV)
+    s = torch.from_numpy(synth.random_settings(rng, B, n)).to(DEV)
+    f = synth.porter_thomas_freqs_torch(961, B, 1 << n, synth.dirichlet_weights(rng, 4), 1_000_000, DEV)
+    inst = api.Instance(atoms, w, s, f)
+    ref = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8)
+    got = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=getattr(api, path_name))
+    pr, _ = api.qst_forward(h, [inst], want_probs=True)
+    pg, _ = api.qst_forward(h, [inst], want_probs=True, path=getattr(api, path_name))
+    torch.cuda.synchronize()
+    tol = TIGHT[path_name]
+    assert abs(float(got[0][0]) - float(ref[0][0])) <= tol * abs(float(ref[0][0]))
+    assert close(pg[0].cpu().numpy(), pr[0].cpu().numpy(), tol)
+    a, b = got[1][0].cpu().numpy(), ref[1][0].cpu().numpy()
+    for r in (0, 5, 15):
+        assert close(a[r], b[r], tol), (r, rel(a[r], b[r]))
+    assert close(got[2][0].cpu().numpy(), ref[2][0].cpu().numpy(), tol)
