@@ -303,8 +303,10 @@ def main():
         torch.cuda.synchronize()
         fused_ms = (time.perf_counter() - t0) * 1e3
         extras["speedup_vs_plain"] = round(plain_ms / fused_ms, 2)
-        # MFMA tile paths (one pass per 4-qubit group, FP16 / BF16 operands)
-        for name, pth in (("tile_f16", api.PATH_TILE_F16), ("tile_bf16", api.PATH_TILE_BF16)):
+        # MFMA tile paths (one pass per 4-qubit group, FP16 / BF16 operands) and the staged path with
+        # BF16 intermediates (tolerance 1e-2 variants)
+        for name, pth in (("tile_f16", api.PATH_TILE_F16), ("tile_bf16", api.PATH_TILE_BF16),
+                          ("butterfly_bf16", api.PATH_BUTTERFLY_BF16)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=pth, out=[grad])

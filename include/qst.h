@@ -92,7 +92,10 @@ typedef enum {
   QST_PATH_TILE_F16 = 4,      /* one HBM pass per 4-qubit group: 16x16 complex Kronecker
                                  tiles on the matrix cores, FP16 operands (scaled per
                                  16x16 block), FP32 accumulation; complex64 atoms        */
-  QST_PATH_TILE_BF16 = 5      /* the same with BF16 operands (high and low parts)         */
+  QST_PATH_TILE_BF16 = 5,     /* the same with BF16 operands (high and low parts)         */
+  QST_PATH_BUTTERFLY_BF16 = 6 /* staged butterflies in FP32 with the setting-batch
+                                 intermediates stored in BF16: half their HBM traffic;
+                                 complex64 atoms, error about 1e-3 (tolerance 1e-2)      */
 } qst_path;
 
 /* One independent tomography instance (the arguments of the paper's problem

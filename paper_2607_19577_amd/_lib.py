@@ -19,7 +19,8 @@ STATUS_NAMES = {
     5: "QST_ERR_DEVICE", 6: "QST_ERR_OOM", 7: "QST_ERR_NUMERIC", 8: "QST_ERR_CAPTURE",
 }
 LOSS_CE, LOSS_LS, LOSS_NONE = 0, 1, 2
-PATH_AUTO, PATH_BUTTERFLY_F32, PATH_BUTTERFLY_F64, PATH_PLAIN_F32, PATH_TILE_F16, PATH_TILE_BF16 = range(6)
+(PATH_AUTO, PATH_BUTTERFLY_F32, PATH_BUTTERFLY_F64, PATH_PLAIN_F32, PATH_TILE_F16, PATH_TILE_BF16,
+ PATH_BUTTERFLY_BF16) = range(7)
 
 # Entry points declared in include/qst.h (checked against the header by the tests).
 EXPORTS = (

@@ -13,18 +13,19 @@ from typing import List, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (LOSS_CE, LOSS_LS, LOSS_NONE, PATH_AUTO, PATH_BUTTERFLY_F32, PATH_BUTTERFLY_F64, PATH_PLAIN_F32,
-                   PATH_TILE_BF16, PATH_TILE_F16, QSTError, QstInstance)
+from ._lib import (LOSS_CE, LOSS_LS, LOSS_NONE, PATH_AUTO, PATH_BUTTERFLY_BF16, PATH_BUTTERFLY_F32,
+                   PATH_BUTTERFLY_F64, PATH_PLAIN_F32, PATH_TILE_BF16, PATH_TILE_F16, QSTError, QstInstance)
 
 __all__ = [
     "Handle", "Instance", "qst_forward", "qst_backward", "qst_reweight_simplex", "qst_refactor", "qst_plan",
     "LOSS_CE", "LOSS_LS", "LOSS_NONE", "PATH_AUTO", "PATH_BUTTERFLY_F32", "PATH_BUTTERFLY_F64", "PATH_PLAIN_F32",
-    "PATH_TILE_F16", "PATH_TILE_BF16", "QSTError",
+    "PATH_TILE_F16", "PATH_TILE_BF16", "PATH_BUTTERFLY_BF16", "QSTError",
 ]
 
 _C_OF_PATH = {
     PATH_AUTO: torch.complex64, PATH_BUTTERFLY_F32: torch.complex64, PATH_BUTTERFLY_F64: torch.complex128,
     PATH_PLAIN_F32: torch.complex64, PATH_TILE_F16: torch.complex64, PATH_TILE_BF16: torch.complex64,
+    PATH_BUTTERFLY_BF16: torch.complex64,
 }
 
 

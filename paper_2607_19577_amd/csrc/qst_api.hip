@@ -119,7 +119,7 @@ qst_status ensure_ws(qst_handle* h, size_t bytes) {
 
 int elem_of(qst_path p) { return p == QST_PATH_BUTTERFLY_F64 ? 8 : 4; }
 
-bool path_valid(int p) { return p >= QST_PATH_AUTO && p <= QST_PATH_TILE_BF16; }
+bool path_valid(int p) { return p >= QST_PATH_AUTO && p <= QST_PATH_BUTTERFLY_BF16; }
 
 // Paths that keep every (setting, atom) vector in HBM and make one pass per qubit
 // (plain) or per group of four qubits (MFMA tiles).
@@ -144,8 +144,10 @@ int env_tile_bits(int which) {
 }
 
 // Geometry of the staged path for (n, R, B).
-qst_status make_geometry(qst_handle* h, int n, int R, int B, int elem, Geometry& g) {
+qst_status make_geometry(qst_handle* h, int n, int R, int B, qst_path path, Geometry& g) {
+  const int elem = elem_of(path);
   g = Geometry{};
+  g.h16 = path == QST_PATH_BUTTERFLY_BF16;
   g.n = n;
   g.R = R;
   g.B = B;
@@ -201,7 +203,7 @@ void set_grid(qst_handle* h, Geometry& g, int S) {
   const long long chunks = (long long)S << g.n_hi;
   int per_cu = 1;
   if (h->device >= 0) {
-    const auto key = std::make_tuple(g.n_lo, g.n_hi > 0 ? 1 : 0, g.R, g.elem);
+    const auto key = std::make_tuple(g.n_lo, (g.n_hi > 0 ? 1 : 0) | (g.h16 ? 2 : 0), g.R, g.elem);
     auto it = h->occupancy.find(key);
     if (it == h->occupancy.end()) it = h->occupancy.emplace(key, qst::lo_blocks_per_cu(g)).first;
     per_cu = it->second;
@@ -247,7 +249,7 @@ long long nslots_of(const Geometry& g, qst_path path) {
 WsLayout layout_ws(const Geometry& g, int S, qst_path path, bool with_gneg, size_t base = 0) {
   WsLayout L{};
   size_t o = base;
-  const size_t vec = (size_t)S * g.R * g.D * 2 * g.elem;
+  const size_t vec = (size_t)S * g.R * g.D * 2 * (g.h16 ? 2 : g.elem);
   L.pc = o;
   o = al256(o + (size_t)g.B * 8);
   L.X = o;
@@ -326,7 +328,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   const qst_instance& in = *rs.in;
   const qst_path path = rs.path;
   Geometry g;
-  qst_status st = make_geometry(h, in.n_qubits, in.rank, in.n_settings, elem_of(path), g);
+  qst_status st = make_geometry(h, in.n_qubits, in.rank, in.n_settings, path, g);
   if (st != QST_OK) return st;
   int S = rs.S_override > 0 ? std::min(rs.S_override, g.B) : default_S(g);
   if (rs.S_override <= 0) {
@@ -518,7 +520,7 @@ qst_status batch_layout(qst_handle* h, const std::vector<const RunSpec*>& rs, bo
     rmax = std::max(rmax, (int)r->in->rank);
     total += r->in->n_settings;
   }
-  qst_status st = make_geometry(h, n, rmax, (int)std::min<long long>(total, 1 << 30), elem, L.g);
+  qst_status st = make_geometry(h, n, rmax, (int)std::min<long long>(total, 1 << 30), rs[0]->path, L.g);
   if (st != QST_OK) return st;
   if (L.g.n_hi != 0) return set_err(h, QST_ERR_SHAPE, "batched instance does not fit one chunk");
   set_grid(h, L.g, (int)std::min<long long>(total, 1 << 30));
@@ -532,7 +534,7 @@ qst_status batch_layout(qst_handle* h, const std::vector<const RunSpec*>& rs, bo
     L.pc.push_back(o);
     o = al256(o + (size_t)in.n_settings * 8);
     L.W.push_back(o);
-    if (adjoint) o = al256(o + (size_t)in.n_settings * in.rank * D * 2 * elem);
+    if (adjoint) o = al256(o + (size_t)in.n_settings * in.rank * D * 2 * (L.g.h16 ? 2 : elem));
     L.part.push_back(o);
     o = al256(o + (size_t)(in.rank + 1) * L.g.grid_lo * 8);
   }
@@ -564,6 +566,7 @@ qst_status run_batch(qst_handle* h, const std::vector<const RunSpec*>& rs) {
   qst::SumBatch sb{};
   sb.count = count;
   sb.elem = L.g.elem;
+  sb.h16 = L.g.h16 ? 1 : 0;
   qst::RowBatch rb{};
   rb.count = count;
   rb.rmax = L.g.R;
@@ -653,7 +656,7 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
   std::vector<const RunSpec*> single;
   for (const RunSpec& r : specs) {
     Geometry g;
-    qst_status st = make_geometry(h, r.in->n_qubits, r.in->rank, r.in->n_settings, elem_of(r.path), g);
+    qst_status st = make_geometry(h, r.in->n_qubits, r.in->rank, r.in->n_settings, r.path, g);
     if (st != QST_OK) return st;
     if (specs.size() > 1 && batchable(g, r.path) && r.in->settings_per_batch <= 0)
       groups[r.in->n_qubits].push_back(&r);
@@ -682,7 +685,7 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
   for (const RunSpec* r : single) {
     if (need) {
       Geometry g;
-      qst_status st = make_geometry(h, r->in->n_qubits, r->in->rank, r->in->n_settings, elem_of(r->path), g);
+      qst_status st = make_geometry(h, r->in->n_qubits, r->in->rank, r->in->n_settings, r->path, g);
       if (st != QST_OK) return st;
       int S = default_S(g);
       auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)r->path));
@@ -893,7 +896,7 @@ qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_pat
     st = validate_instance(h, inst[i], path, false);
     if (st != QST_OK) return st;
     Geometry g;
-    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, elem_of(path), g);
+    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, path, g);
     if (st != QST_OK) return st;
     int S = default_S(g);
     if (h->device < 0) continue;
@@ -1003,7 +1006,7 @@ qst_status qst_forward(qst_handle* h, const qst_instance* inst, int n_inst, void
     st = validate_instance(h, inst[i], path, loss != nullptr);
     if (st != QST_OK) return st;
     Geometry g;
-    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, elem_of(path), g);
+    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, path, g);
     if (st != QST_OK) return st;
   }
   st = device_gate(h);
@@ -1047,7 +1050,7 @@ qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, con
     if (!aligned(atom_grad[i], ea)) return set_err(h, QST_ERR_ALIGN, "atom_grad misaligned");
     if (atom_grad[i] == inst[i].atoms) return set_err(h, QST_ERR_INVALID_ARG, "atom_grad aliases atoms");
     Geometry g;
-    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, elem_of(path), g);
+    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, path, g);
     if (st != QST_OK) return st;
   }
   st = device_gate(h);
@@ -1108,7 +1111,7 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
   if (st != QST_OK) return st;
   {
     Geometry gchk;
-    st = make_geometry(h, inst->n_qubits, inst->rank, inst->n_settings, elem_of(path), gchk);
+    st = make_geometry(h, inst->n_qubits, inst->rank, inst->n_settings, path, gchk);
     if (st != QST_OK) return st;
   }
   st = device_gate(h);
@@ -1118,9 +1121,9 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
   const int n = inst->n_qubits, R = inst->rank, B = inst->n_settings;
   const long long D = 1ll << n;
   Geometry gR, g1;
-  st = make_geometry(h, n, R, B, elem, gR);
+  st = make_geometry(h, n, R, B, path, gR);
   if (st != QST_OK) return st;
-  st = make_geometry(h, n, 1, B, elem, g1);
+  st = make_geometry(h, n, 1, B, path, g1);
   if (st != QST_OK) return st;
   const int k_max = (int)std::min<long long>(n_lanczos, D);
   hipStream_t s = h->stream;

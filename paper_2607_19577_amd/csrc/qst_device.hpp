@@ -440,6 +440,36 @@ __device__ __forceinline__ void bstore2(double x, double y, rsrc_t rs, uint32_t 
   __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)voff, (int)soff, 0);
 }
 
+// BF16 storage of intermediate amplitudes: one complex number per 32-bit word,
+// real part in the low half, each rounded to nearest even (finite values).
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ void bload2h(float& x, float& y, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0);
+  x = __uint_as_float(w << 16);
+  y = __uint_as_float(w & 0xffff0000u);
+}
+__device__ __forceinline__ void bstore2h(float x, float y, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(bf16_bits(x) | (bf16_bits(y) << 16), rs, (int)voff, (int)soff, 0);
+}
+// Load or store a complex number kept in BF16 (H16) or in the working precision.
+template <bool H16, typename T>
+__device__ __forceinline__ void ld_cs(T& x, T& y, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  if constexpr (H16)
+    bload2h(x, y, rs, voff, soff);
+  else
+    bload2(x, y, rs, voff, soff);
+}
+template <bool H16, typename T>
+__device__ __forceinline__ void st_cs(T x, T y, rsrc_t rs, uint32_t voff, uint32_t soff) {
+  if constexpr (H16)
+    bstore2h(x, y, rs, voff, soff);
+  else
+    bstore2(x, y, rs, voff, soff);
+}
+
 // Layout chain of a block of 2^NB amplitudes with 2^LOGV registers per thread:
 // lo(0) = NB - LOGV, then LOGV bits lower per step down to 0.
 template <int NB, int LOGV>

@@ -24,6 +24,7 @@ struct Geometry {
   int S;
   int elem;      // bytes per real (4 or 8)
   int split_adj; // work-groups per adjoint tile at batch size S (partial-sum slices in the workspace)
+  bool h16;      // the setting-batch intermediates X and W are stored in BF16
 };
 
 struct LoArgs {
@@ -82,6 +83,7 @@ struct DecodeBatch {
 struct SumBatch {  // grad_k[e] = sum_s W_k[s][e], e < R_k D
   int count;
   int elem;
+  int h16;  // W in BF16
   long long total;
   long long begin[kBatchMax + 1];
   const void* W[kBatchMax];

@@ -70,18 +70,24 @@ size_t lo_lds_bytes(const Geometry& g) {
 
 // ------------------------------------------------------------------ stage dispatch
 hipError_t launch_stage_lo_f32(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
+hipError_t launch_stage_lo_h16(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
 hipError_t launch_stage_lo_f64(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
 int lo_occupancy_f32(const Geometry& g);
+int lo_occupancy_h16(const Geometry& g);
 int lo_occupancy_f64(const Geometry& g);
 
 hipError_t launch_stage_lo(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
   if (m.count < 1 || m.count > kBatchMax || m.rmax != g.R) return hipErrorInvalidValue;
-  return g.elem == 4 ? launch_stage_lo_f32(g, m, adjoint, st) : launch_stage_lo_f64(g, m, adjoint, st);
+  if (g.elem != 4) return launch_stage_lo_f64(g, m, adjoint, st);
+  return g.h16 ? launch_stage_lo_h16(g, m, adjoint, st) : launch_stage_lo_f32(g, m, adjoint, st);
 }
 
 // Resident low-stage work-groups per compute unit (the persistent grid is this
 // times the number of compute units).
-int lo_blocks_per_cu(const Geometry& g) { return g.elem == 4 ? lo_occupancy_f32(g) : lo_occupancy_f64(g); }
+int lo_blocks_per_cu(const Geometry& g) {
+  if (g.elem != 4) return lo_occupancy_f64(g);
+  return g.h16 ? lo_occupancy_h16(g) : lo_occupancy_f32(g);
+}
 
 size_t hi_lds_bytes(const Geometry& g) {
   const size_t N = (size_t)1 << g.t;
@@ -92,30 +98,40 @@ size_t hi_lds_bytes(const Geometry& g) {
 // sum_s W[s][e] with four interleaved partial sums (more loads in flight per thread),
 // combined in a fixed order; the single-instance and the batched kernels share it, so
 // both give the same bits.
-template <typename T>
-__device__ __forceinline__ cx<T> settings_sum(const cx<T>* __restrict__ W, int S, long long RD, long long e) {
+template <typename T, bool H16>
+__device__ __forceinline__ cx<T> w_at(const void* W, long long i) {
+  if constexpr (H16) {
+    const uint32_t w = reinterpret_cast<const uint32_t*>(W)[i];
+    return cx<T>{__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
+  } else {
+    return reinterpret_cast<const cx<T>*>(W)[i];
+  }
+}
+
+template <typename T, bool H16>
+__device__ __forceinline__ cx<T> settings_sum(const void* __restrict__ W, int S, long long RD, long long e) {
   cx<T> a[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   int s = 0;
   for (; s + 4 <= S; s += 4) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const cx<T> w = W[(long long)(s + j) * RD + e];
+      const cx<T> w = w_at<T, H16>(W, (long long)(s + j) * RD + e);
       a[j].x += w.x;
       a[j].y += w.y;
     }
   }
   for (int j = 0; s < S; ++s, ++j) {
-    const cx<T> w = W[(long long)s * RD + e];
+    const cx<T> w = w_at<T, H16>(W, (long long)s * RD + e);
     a[j].x += w.x;
     a[j].y += w.y;
   }
   return cx<T>{(a[0].x + a[1].x) + (a[2].x + a[3].x), (a[0].y + a[1].y) + (a[2].y + a[3].y)};
 }
 
-template <typename T>
-__global__ void k_sum_settings(const cx<T>* __restrict__ W, int S, long long RD, cx<T>* __restrict__ grad, int first) {
+template <typename T, bool H16>
+__global__ void k_sum_settings(const void* __restrict__ W, int S, long long RD, cx<T>* __restrict__ grad, int first) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < RD; e += (long long)gridDim.x * blockDim.x) {
-    const cx<T> acc = settings_sum<T>(W, S, RD, e);
+    const cx<T> acc = settings_sum<T, H16>(W, S, RD, e);
     if (first) {
       grad[e] = acc;
     } else {
@@ -130,12 +146,12 @@ hipError_t launch_sum_settings(const Geometry& g, const void* W, int S, void* gr
   const int bs = 256;
   long long nb = (RD + bs - 1) / bs;
   if (nb > 8192) nb = 8192;
-  if (g.elem == 4)
-    k_sum_settings<float><<<(unsigned)nb, bs, 0, st>>>(reinterpret_cast<const float2*>(W), S, RD,
-                                                        reinterpret_cast<float2*>(grad), first);
+  if (g.elem == 4 && g.h16)
+    k_sum_settings<float, true><<<(unsigned)nb, bs, 0, st>>>(W, S, RD, reinterpret_cast<float2*>(grad), first);
+  else if (g.elem == 4)
+    k_sum_settings<float, false><<<(unsigned)nb, bs, 0, st>>>(W, S, RD, reinterpret_cast<float2*>(grad), first);
   else
-    k_sum_settings<double><<<(unsigned)nb, bs, 0, st>>>(reinterpret_cast<const double2*>(W), S, RD,
-                                                         reinterpret_cast<double2*>(grad), first);
+    k_sum_settings<double, false><<<(unsigned)nb, bs, 0, st>>>(W, S, RD, reinterpret_cast<double2*>(grad), first);
   return hipGetLastError();
 }
 
@@ -343,13 +359,13 @@ hipError_t launch_decode_batch(const DecodeBatch& b, int* flag, hipStream_t st) 
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool H16>
 __global__ void k_sum_batch(const SumBatch b) {
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < b.total;
        t += (long long)gridDim.x * blockDim.x) {
     const int k = batch_find(b.begin, b.count, t);
     const long long e = t - b.begin[k];
-    reinterpret_cast<cx<T>*>(b.grad[k])[e] = settings_sum<T>(reinterpret_cast<const cx<T>*>(b.W[k]), b.S[k], b.RD[k], e);
+    reinterpret_cast<cx<T>*>(b.grad[k])[e] = settings_sum<T, H16>(b.W[k], b.S[k], b.RD[k], e);
   }
 }
 
@@ -358,10 +374,12 @@ hipError_t launch_sum_batch(const SumBatch& b, hipStream_t st) {
   const int bs = 256;
   long long nb = (b.total + bs - 1) / bs;
   if (nb > 8192) nb = 8192;
-  if (b.elem == 4)
-    k_sum_batch<float><<<(unsigned)nb, bs, 0, st>>>(b);
+  if (b.elem == 4 && b.h16)
+    k_sum_batch<float, true><<<(unsigned)nb, bs, 0, st>>>(b);
+  else if (b.elem == 4)
+    k_sum_batch<float, false><<<(unsigned)nb, bs, 0, st>>>(b);
   else
-    k_sum_batch<double><<<(unsigned)nb, bs, 0, st>>>(b);
+    k_sum_batch<double, false><<<(unsigned)nb, bs, 0, st>>>(b);
   return hipGetLastError();
 }
 

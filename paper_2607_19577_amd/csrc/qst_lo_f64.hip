@@ -11,7 +11,7 @@ hipError_t launch_stage_lo_f64(const Geometry& g, const LoBatch& m, bool adjoint
   if (g.n_hi != 0) return hipErrorInvalidValue;
   switch (g.n_lo) {
 #define QST_P(N) \
-  case N: return launch_lo_n<double, N, true>(g, m, adjoint, st);
+  case N: return launch_lo_n<double, N, true, false>(g, m, adjoint, st);
     QST_LO64_CASES(QST_P)
 #undef QST_P
   }
@@ -21,7 +21,7 @@ hipError_t launch_stage_lo_f64(const Geometry& g, const LoBatch& m, bool adjoint
 int lo_occupancy_f64(const Geometry& g) {
   switch (g.n_lo) {
 #define QST_P(N) \
-  case N: return lo_occupancy_n<double, N, true>(g);
+  case N: return lo_occupancy_n<double, N, true, false>(g);
     QST_LO64_CASES(QST_P)
 #undef QST_P
   }

@@ -139,7 +139,9 @@ __device__ __forceinline__ void apply_phase(T (&x)[1 << LOGV], T (&y)[1 << LOGV]
 // prefetches the next chunk's amplitudes and data row while it works on the
 // current one.  Its loss and weight-gradient partials go to one slot per
 // (batch, work-group), so the final sums do not depend on timing.
-template <typename T, int N_LO, bool ADJ, bool PHASE>
+// H16: the setting-batch intermediates X (input, when the state has high bits) and W
+// (output) are stored in BF16; arithmetic stays in T.
+template <typename T, int N_LO, bool ADJ, bool PHASE, bool H16>
 __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
   using C2 = cx<T>;
   constexpr int LOGV = N_LO < 5 ? N_LO : 5;
@@ -152,7 +154,9 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
   using CH = Chain<N_LO, LOGV>;
   constexpr int NL = CH::count();
   constexpr int LO0 = CH::lo(0);
-  constexpr uint32_t CB = sizeof(C2);
+  constexpr bool H16_IN = H16 && !PHASE;                      // X in BF16 (atoms are read as given)
+  constexpr uint32_t CBI = H16_IN ? 4u : (uint32_t)sizeof(C2);  // bytes per input complex
+  constexpr uint32_t CBO = H16 ? 4u : (uint32_t)sizeof(C2);     // bytes per output complex
   constexpr bool WL = LOG_TA <= 6;  // the threads of one atom form (part of) one wavefront
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
@@ -183,8 +187,8 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
     return k;
   };
   // Buffer extent of one chunk (all atoms of the instance) and this thread's offset.
-  auto extent = [&](const LoArgs& a) { return (uint32_t)(((long long)(a.R - 1) * a.D + U) * CB); };
-  auto voff = [&](const LoArgs& a) { return (uint32_t)(((long long)atom * a.D + pos0) * CB); };
+  auto extent = [&](const LoArgs& a, uint32_t cb) { return (uint32_t)(((long long)(a.R - 1) * a.D + U) * cb); };
+  auto voff = [&](const LoArgs& a, uint32_t cb) { return (uint32_t)(((long long)atom * a.D + pos0) * cb); };
 
   double loss_acc = 0.0, h_acc = 0.0;
   int cur = -1;            // instance whose partials are being accumulated
@@ -232,12 +236,13 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
     const int cl = c - m.begin[k];
     const int s = cl >> a.n_hi;
     const int h = cl & ((1 << a.n_hi) - 1);
-    const C2* sbase = reinterpret_cast<const C2*>(a.src) + (long long)s * a.src_set_stride + ((long long)h << N_LO);
+    const unsigned char* sbase = reinterpret_cast<const unsigned char*>(a.src) +
+                                 ((long long)s * a.src_set_stride + ((long long)h << N_LO)) * CBI;
     // threads of atoms beyond this instance's rank lie outside the extent: they read zeros
-    const rsrc_t rs = make_rsrc(sbase, extent(a));
-    const uint32_t vo0 = voff(a);
+    const rsrc_t rs = make_rsrc(sbase, extent(a, CBI));
+    const uint32_t vo0 = voff(a, CBI);
 #pragma unroll
-    for (int i = 0; i < V; ++i) bload2(bx[i], by[i], rs, vo0, (uint32_t)(i << LO0) * CB);
+    for (int i = 0; i < V; ++i) ld_cs<H16_IN>(bx[i], by[i], rs, vo0, (uint32_t)(i << LO0) * CBI);
     if (a.grad_p != nullptr || a.loss_kind != 2) {
       const long long row = (long long)(a.b0 + s) * a.D + ((long long)h << N_LO);
 #pragma unroll
@@ -352,11 +357,11 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
       if constexpr (!WL) __syncthreads();  // every thread has read g before the planes are reused
       adj_chain<NL - 1, CH, WL, LOGV>(x, y, re, im, tau, pc);
       if constexpr (PHASE) apply_phase<true, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
-      C2* dbase = reinterpret_cast<C2*>(a.dst) + (long long)s * a.R * D + ((long long)h << N_LO);
-      const rsrc_t rd = make_rsrc(dbase, extent(a));
-      const uint32_t vo0 = voff(a);
+      unsigned char* dbase = reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + ((long long)h << N_LO)) * CBO;
+      const rsrc_t rd = make_rsrc(dbase, extent(a, CBO));
+      const uint32_t vo0 = voff(a, CBO);
 #pragma unroll
-      for (int i = 0; i < V; ++i) bstore2(x[i], y[i], rd, vo0, (uint32_t)(i << LO0) * CB);
+      for (int i = 0; i < V; ++i) st_cs<H16>(x[i], y[i], rd, vo0, (uint32_t)(i << LO0) * CBO);
       if constexpr (!WL) __syncthreads();
     }
   };
@@ -381,33 +386,33 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
   }
 }
 
-template <typename T, int N_LO, bool PHASE>
+template <typename T, int N_LO, bool PHASE, bool H16>
 hipError_t launch_lo_n(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
   constexpr int LOGV = N_LO < 5 ? N_LO : 5;
   const int nthr = m.rmax << (N_LO - LOGV);
   const size_t lds = lo_lds_bytes(g);
   const unsigned grid = (unsigned)g.grid_lo;
   if (adjoint) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_lo<T, N_LO, true, PHASE><<<grid, nthr, lds, st>>>(m);
+    k_stage_lo<T, N_LO, true, PHASE, H16><<<grid, nthr, lds, st>>>(m);
   } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, false, PHASE>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, false, PHASE, H16>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_lo<T, N_LO, false, PHASE><<<grid, nthr, lds, st>>>(m);
+    k_stage_lo<T, N_LO, false, PHASE, H16><<<grid, nthr, lds, st>>>(m);
   }
   return hipGetLastError();
 }
 
-template <typename T, int N_LO, bool PHASE>
+template <typename T, int N_LO, bool PHASE, bool H16>
 int lo_occupancy_n(const Geometry& g) {
   constexpr int LOGV = N_LO < 5 ? N_LO : 5;
   const int nthr = g.R << (N_LO - LOGV);
   const size_t lds = lo_lds_bytes(g);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE>),
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_stage_lo<T, N_LO, true, PHASE>, nthr, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_stage_lo<T, N_LO, true, PHASE, H16>, nthr, lds) !=
       hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
@@ -429,7 +434,8 @@ constexpr uint32_t rows_mask(int lo, int c, int top) {
   return m;
 }
 
-template <int TB, int N_HI, bool ADJ>
+// H16: X (forward output) and W (adjoint input) are stored in BF16.
+template <int TB, int N_HI, bool ADJ, bool H16>
 __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   using T = float;
   using C2 = float2;
@@ -461,6 +467,8 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   const uint32_t cbase = (uint32_t)cb << C;  // index of the tile origin within the atom
   const long long origin = (long long)r * D + cbase;
   const uint32_t vbytes = (uint32_t)((D - cbase) * CB);
+  constexpr uint32_t CBH = H16 ? 4u : CB;  // bytes per complex of X and W
+  const uint32_t vbytes_h = (uint32_t)((D - cbase) * CBH);
   const uint32_t t0 = tile_off(lay_pos<LOGV>(tid, 0, LO0), C, n_lo);
   const uint32_t tf = tile_off(lay_pos<LOGV>(tid, 0, LOF), C, n_lo);
   const uint32_t vo0 = t0 * CB;
@@ -490,9 +498,10 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
         xform_xz<LOGV, M1>(x, y, layout_codes<LOGV>(pc, LO1, LO1, LO0, C, n_lo));
       }
-      const rsrc_t rx = make_rsrc(reinterpret_cast<C2*>(a.dst) + (long long)s * a.R * D + origin, vbytes);
+      const rsrc_t rx =
+          make_rsrc(reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + origin) * CBH, vbytes_h);
 #pragma unroll
-      for (int i = 0; i < V; ++i) bstore2(x[i], y[i], rx, vof, offf(i) * CB);
+      for (int i = 0; i < V; ++i) st_cs<H16>(x[i], y[i], rx, tf * CBH, offf(i) * CBH);
     }
   } else {
     T ax[V], ay[V];
@@ -502,10 +511,11 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
     // while the other is transformed in place.
     T px[V], py[V], qx[V], qy[V];
     auto issue = [&](int s, T (&bx)[V], T (&by)[V]) __attribute__((always_inline)) {
-      const rsrc_t rw = make_rsrc(reinterpret_cast<const C2*>(a.src) + (long long)s * a.R * D + origin, vbytes);
+      const rsrc_t rw = make_rsrc(
+          reinterpret_cast<const unsigned char*>(a.src) + ((long long)s * a.R * D + origin) * CBH, vbytes_h);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        bload2(bx[i], by[i], rw, vo0, off0(i) * CB);
+        ld_cs<H16>(bx[i], by[i], rw, t0 * CBH, off0(i) * CBH);
       }
     };
     auto body = [&](int s, T (&x)[V], T (&y)[V]) __attribute__((always_inline)) {
@@ -550,19 +560,19 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   }
 }
 
-template <int TB, int N_HI>
+template <int TB, int N_HI, bool H16>
 hipError_t launch_hi_n(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st) {
   const int nthr = 1 << (TB - 5);
   const size_t lds = hi_lds_bytes(g);
   const unsigned grid = (unsigned)((g.R << (g.n_lo - g.c)) * a.nsplit);
   if (adjoint) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, true>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, true, H16>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_hi<TB, N_HI, true><<<grid, nthr, lds, st>>>(a);
+    k_stage_hi<TB, N_HI, true, H16><<<grid, nthr, lds, st>>>(a);
   } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, false>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, false, H16>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_hi<TB, N_HI, false><<<grid, nthr, lds, st>>>(a);
+    k_stage_hi<TB, N_HI, false, H16><<<grid, nthr, lds, st>>>(a);
   }
   return hipGetLastError();
 }

@@ -262,3 +262,6 @@ def test_full_size_gradient_on_setting_subset(h, big):
                 freqs=big["freqs_dev"][rows].cpu().numpy())
     ref = oracle(case, born.LOSS_CE, 1e-8, tier="axis")
     _check(_run(h, case, api.LOSS_CE, api.PATH_BUTTERFLY_F32), ref, TOL32, "n=20 subset")
+    # the MFMA tile paths on the same sampled settings (tolerance of the FP16/BF16 variants)
+    for path in (api.PATH_TILE_F16, api.PATH_TILE_BF16):
+        _check(_run(h, case, api.LOSS_CE, path), ref, 1e-2, f"n=20 subset tile path {path}")

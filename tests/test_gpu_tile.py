@@ -6,6 +6,10 @@ for probabilities, loss, atom and weight gradients.  The BF16 path splits each
 amplitude into two BF16 parts and is checked at 1e-4 as well; the FP16 path scales
 each 16x16 block before rounding and is checked at 3e-3.  At the full n=20, R=16
 shape the tile paths are compared with the FP32 butterfly path on a setting subset.
+
+The staged butterfly path with BF16 intermediates (FP32 arithmetic, the setting-batch
+amplitudes X and W stored in BF16) is checked at 1e-2, including several batches,
+batched small instances and the full n=20, R=16 shape on a setting subset.
 """
 import numpy as np
 import pytest
@@ -100,3 +104,67 @@ def test_tile_path_full_size_subset(h, path_name):
     for r in (0, 5, 15):
         assert close(a[r], b[r], tol), (r, rel(a[r], b[r]))
     assert close(got[2][0].cpu().numpy(), ref[2][0].cpu().numpy(), tol)
+
+
+# ---------------------------------------------------------------- FP32 butterflies with BF16 intermediates
+TOL_BF16X = 1e-2
+
+
+@pytest.mark.parametrize("n,R,B,spb", [
+    (6, 3, 9, 0),      # whole state in one chunk: W in BF16, settings summed from BF16
+    (12, 5, 17, 0),    # tile stages with one high bit
+    (15, 16, 11, 4),   # tile stages, several batches
+    (17, 3, 9, 2),     # n_lo = 12, five batches
+])
+def test_bf16_intermediates_match_oracle(h, n, R, B, spb):
+    from paper_2607_19577_amd import api
+
+    case = make_case(970 + n, n, R, B, shots=5000)
+    inst = to_device(case, DEV)
+    inst.settings_per_batch = spb
+    probs, _ = api.qst_forward(h, [inst], want_probs=True, path=api.PATH_BUTTERFLY_BF16)
+    lt, ag, wg = api.qst_backward(h, [inst], loss=born.LOSS_CE, eps=1e-8, path=api.PATH_BUTTERFLY_BF16)
+    torch.cuda.synchronize()
+    Lr, pr, gar, gwr = oracle(case, born.LOSS_CE, 1e-8, tier="axis")
+    assert abs(float(lt[0]) - Lr) <= TOL_BF16X * abs(Lr)
+    assert close(probs[0].cpu().numpy(), pr, TOL_BF16X), rel(probs[0].cpu().numpy(), pr)
+    g = ag[0].cpu().numpy()
+    for r in range(R):
+        assert close(g[r], gar[r], TOL_BF16X), (r, rel(g[r], gar[r]))
+    assert close(wg[0].cpu().numpy(), gwr, TOL_BF16X), rel(wg[0].cpu().numpy(), gwr)
+
+
+def test_bf16_intermediates_batched_instances(h):
+    """Several small instances in one call (one launch per step) on the BF16-intermediate path."""
+    from paper_2607_19577_amd import api
+
+    cases = [make_case(980 + i, 7, R, B, shots=5000) for i, (R, B) in enumerate([(2, 5), (5, 7), (8, 3)])]
+    insts = [to_device(c, DEV) for c in cases]
+    lt, ag, wg = api.qst_backward(h, insts, loss=born.LOSS_CE, eps=1e-8, path=api.PATH_BUTTERFLY_BF16)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        Lr, _, gar, gwr = oracle(c, born.LOSS_CE, 1e-8)
+        assert abs(float(lt[i]) - Lr) <= TOL_BF16X * abs(Lr)
+        g = ag[i].cpu().numpy()
+        for r in range(g.shape[0]):
+            assert close(g[r], gar[r], TOL_BF16X), (i, r, rel(g[r], gar[r]))
+
+
+def test_bf16_intermediates_full_size_subset(h):
+    """n=20, R=16 on four settings against the FP32 butterfly path."""
+    from paper_2607_19577_amd import api
+
+    rng = synth.make_rng(990)
+    n, R, B = 20, 16, 4
+    atoms = torch.from_numpy(synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64)).to(DEV)
+    w = torch.from_numpy(synth.dirichlet_weights(rng, R)).to(DEV)
+    s = torch.from_numpy(synth.random_settings(rng, B, n)).to(DEV)
+    f = synth.porter_thomas_freqs_torch(991, B, 1 << n, synth.dirichlet_weights(rng, 4), 1_000_000, DEV)
+    inst = api.Instance(atoms, w, s, f)
+    ref = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8)
+    got = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=api.PATH_BUTTERFLY_BF16)
+    torch.cuda.synchronize()
+    assert abs(float(got[0][0]) - float(ref[0][0])) <= TOL_BF16X * abs(float(ref[0][0]))
+    a, b = got[1][0].cpu().numpy(), ref[1][0].cpu().numpy()
+    for r in (0, 5, 15):
+        assert close(a[r], b[r], TOL_BF16X), (r, rel(a[r], b[r]))
