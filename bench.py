@@ -187,6 +187,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip refactor / plain-path timings")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--path", default="butterfly_f32", choices=["butterfly_f32", "butterfly_bf16"],
+                    help="path of the timed step: FP32 butterflies (default, the 1e-5 path) or the same with "
+                         "BF16 intermediates (1e-2 variant)")
     ap.add_argument("--batch", type=int, default=0, help="settings per batch (0: library default or --autotune)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only a 1 GiB device copy (counter scale)")
     args = ap.parse_args()
@@ -240,8 +243,11 @@ def main():
     print(f"[bench] inputs resident: atoms {inst.atoms.numel() * 8 / 2**20:.0f} MiB, freqs "
           f"{freqs.numel() * 4 / 2**30:.2f} GiB", file=sys.stderr, flush=True)
 
+    step_path = api.PATH_BUTTERFLY_BF16 if args.path == "butterfly_bf16" else api.PATH_BUTTERFLY_F32
+
     def step():
-        lt, ag, wg = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, project_tangent=True, out=[grad])
+        lt, ag, wg = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, project_tangent=True, out=[grad],
+                                      path=step_path)
         # coefficient step: beta = proj(alpha + eta (A^T c)) with A^T c = -dL/dalpha
         api.qst_reweight_simplex(h, inst.weights, wg[0], -0.5, 1e-3)
         return lt
@@ -271,18 +277,19 @@ def main():
     lo_launches = stages["lo_fused"][0]
     if lo_launches:
         S = B * args.steps / lo_launches  # settings per batch (uniform batches)
-    cb = 8  # bytes per complex64
+    cb = 8  # bytes per complex64 (atoms, gradient)
+    ch = 4 if args.path == "butterfly_bf16" else 8  # bytes per complex of the intermediates X and W
     per_launch_bytes = {
-        "hi_fwd": (R * D * cb + S * R * D * cb) if S else None,
-        "lo_fused": (S * R * D * cb + S * D * 4 + S * R * D * cb) if S else None,
-        "hi_adj": (S * R * D * cb + 2 * R * D * cb) if S else None,
+        "hi_fwd": (R * D * cb + S * R * D * ch) if S else None,
+        "lo_fused": (S * R * D * ch + S * D * 4 + S * R * D * ch) if S else None,
+        "hi_adj": (S * R * D * ch + 2 * R * D * cb) if S else None,
     }
     dom = max(("hi_fwd", "lo_fused", "hi_adj"), key=lambda k: stages[k][1])
     nl, tot_ms = stages[dom]
     avg_ms = tot_ms / max(nl, 1)
     achieved = per_launch_bytes[dom] / (avg_ms * 1e-3) / 1e9 if per_launch_bytes[dom] else None
     names = {"hi_fwd": "k_stage_hi_fwd", "lo_fused": "k_stage_lo_fused", "hi_adj": "k_stage_hi_adj"}
-    traffic = read_traffic(names[dom], args.workload)
+    traffic = read_traffic(names[dom], args.workload) if args.path == "butterfly_f32" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None,
                 "traffic": traffic, "kernel": names[dom], "avg_launch_ms": round(avg_ms, 4),
@@ -335,7 +342,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.path == "butterfly_f32" else "f32 (bf16 intermediates)",
         "data": "synthetic",
         "config": {"workload": f"n={n} qubits, R={R} atoms, B={B} random Pauli settings, {shots} shots/setting, "
                                "complex64 atoms, cross-entropy", "n": n, "R": R, "B": B, "D": D,
