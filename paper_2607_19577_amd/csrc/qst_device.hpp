@@ -22,7 +22,7 @@ template <> struct cx_of<double> { using type = double2; };
 template <typename T> using cx = typename cx_of<T>::type;
 
 // Pauli codes as stored in a setting: X = 0, Y = 1, Z = 2.  Codes 2 and 3 mean
-// "no rotation" inside the 2-bit code words handed to xform().
+// "no rotation" inside the 2-bit code words handed to xform_xz().
 constexpr uint32_t CODE_SKIP = 2u;
 
 // LDS index with one pad slot every 32 elements: a stride-32 access pattern
@@ -57,13 +57,9 @@ __host__ __device__ constexpr int pad_off(int i) {
 // The 1/sqrt2 factors are applied once per setting as the exact power of two
 // 2^(-k_b) on |phi|^2.
 //
-// Each butterfly updates its pair in place: b' is formed first and a' is then
-// recovered as 2a - b' with one fused multiply-add (a' = a + s, b' = a - s).
-// The extra rounding is one ulp of |(a, b)|, well inside the FP32 tolerance,
-// and the form needs no temporaries beyond the pair itself.  Amplitudes are
-// kept as separate real and imaginary register arrays: with the code of each
-// bit known only at run time, the (X, Y, skip) branches then merge without
-// re-pairing registers.
+// These exact rotations serve the single-pass kernels: b' is formed first and
+// a' is then recovered as 2a - b' with one fused multiply-add (a' = a + s,
+// b' = a - s); the extra rounding is one ulp of |(a, b)|.
 template <typename T>
 __device__ __forceinline__ void bf_x(T& ax, T& ay, T& bx, T& by) {
   bx = ax - bx;
@@ -94,115 +90,27 @@ template <typename C2> __device__ __forceinline__ void bf_x(C2& a, C2& b) { bf_x
 template <typename C2> __device__ __forceinline__ void bf_y(C2& a, C2& b) { bf_y(a.x, a.y, b.x, b.y); }
 template <typename C2> __device__ __forceinline__ void bf_yh(C2& a, C2& b) { bf_yh(a.x, a.y, b.x, b.y); }
 
-template <int K, int LOGV, int CODE, bool ADJ, typename T>
-__device__ __forceinline__ void pairs(T (&x)[1 << LOGV], T (&y)[1 << LOGV]) {
-#pragma unroll
-  for (int i = 0; i < (1 << LOGV); ++i) {
-    if (i & (1 << K)) continue;
-    const int j = i | (1 << K);
-    if (CODE == 0) {
-      bf_x(x[i], y[i], x[j], y[j]);
-    } else if (ADJ) {
-      bf_yh(x[i], y[i], x[j], y[j]);
-    } else {
-      bf_y(x[i], y[i], x[j], y[j]);
-    }
-  }
-}
-
-template <int K, int LOGV, bool ADJ, typename T>
-__device__ __forceinline__ void xform_bit(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
-  if constexpr (K < LOGV) {
-    const uint32_t c = (codes >> (2 * K)) & 3u;
-    if (c == 0u) {
-      pairs<K, LOGV, 0, ADJ>(x, y);
-    } else if (c == 1u) {
-      pairs<K, LOGV, 1, ADJ>(x, y);
-    }
-    xform_bit<K + 1, LOGV, ADJ>(x, y, codes);
-  }
-}
-
-// Apply the rotations of the in-register bits; `codes` holds 2 bits per
-// register bit (must be uniform across the work-group).
-template <int LOGV, bool ADJ, typename T>
-__device__ __forceinline__ void xform(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
-  xform_bit<0, LOGV, ADJ>(x, y, codes);
-}
-
-// Branch-free variant for code paths that must not branch per bit.  A row
-// phase on V_b changes neither |V_b psi|^2 nor V_b^dagger (g * V_b psi), so a
-// Z bit may be applied as diag(1,-1) instead of the identity, provided the
-// adjoint pass does the same (diag(1,-1) is its own adjoint).  Then every
-// active bit takes one of three in-register forms selected by uniform
-// coefficients f = [code != Z] and y = [code == Y]:
-//   forward:  s = y ? -i b : b;   a' = a + f s;   b' = f a - s
-//   adjoint:  t = f a - b;        a' = a + f b;   b' = y ? i t : t
-// which give (a+b, a-b) for X, (a-ib, a+ib) resp. (a+b, i(a-b)) for Y and
-// (a, -b) for Z.  Bits outside ACTIVE (not qubits of this pass) are untouched.
-template <int K, int LOGV, bool ADJ, typename T>
-__device__ __forceinline__ void bit_uniform(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t c) {
-  const T f = c < 2u ? T(1) : T(0);
-  const bool isy = c == 1u;
-#pragma unroll
-  for (int i = 0; i < (1 << LOGV); ++i) {
-    if (i & (1 << K)) continue;
-    const int j = i | (1 << K);
-    if (!ADJ) {
-      const T sx = isy ? y[j] : x[j];
-      const T sy = isy ? -x[j] : y[j];
-      const T nbx = fma(f, x[i], -sx);
-      const T nby = fma(f, y[i], -sy);
-      x[i] = fma(f, sx, x[i]);
-      y[i] = fma(f, sy, y[i]);
-      x[j] = nbx;
-      y[j] = nby;
-    } else {
-      const T tx = fma(f, x[i], -x[j]);
-      const T ty = fma(f, y[i], -y[j]);
-      x[i] = fma(f, x[j], x[i]);
-      y[i] = fma(f, y[j], y[i]);
-      x[j] = isy ? -ty : tx;
-      y[j] = isy ? tx : ty;
-    }
-  }
-}
-
-template <int K, int LOGV, bool ADJ, uint32_t ACTIVE, typename T>
-__device__ __forceinline__ void xform_uniform_bit(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
-  if constexpr (K < LOGV) {
-    if constexpr ((ACTIVE >> K) & 1u) bit_uniform<K, LOGV, ADJ>(x, y, (codes >> (2 * K)) & 3u);
-    xform_uniform_bit<K + 1, LOGV, ADJ, ACTIVE>(x, y, codes);
-  }
-}
-
-template <int LOGV, bool ADJ, uint32_t ACTIVE, typename T>
-__device__ __forceinline__ void xform_uniform(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t codes) {
-  xform_uniform_bit<0, LOGV, ADJ, ACTIVE>(x, y, codes);
-}
-
 // Phase-split form (used by the staged kernels).  V_Y = H diag(1, -i) with the
 // diagonal on the input side, and diagonals on different qubits commute with
 // everything else, so for a setting with Y-qubit mask ymask
 //     V_b = (x)_k M_k  *  diag((-i)^popcount(v & ymask)),
-// M_k = H for X and Y bits and, as above, diag(1,-1) for Z bits (a row phase).
-// The kernels apply the per-element phase once per setting where the state
-// enters the rotation (forward) or leaves it (adjoint: the conjugate phase
-// after the M's), and every bit in between takes the same 4-operation
-// butterfly a' = a + f b, b' = f a - b with f = [code != Z]; H and diag(1,-1)
-// are their own adjoints.
+// M_k = H for X and Y bits and the identity for Z bits.  The kernels apply the
+// per-element phase once per setting where the state enters the rotation
+// (forward) or leaves it (adjoint: the conjugate phase after the M's); every
+// X or Y bit in between is the same in-place butterfly a' = a + b,
+// b' = a' - 2b (H is its own adjoint; the extra rounding is one ulp of
+// |(a, b)|), and a Z bit is a uniform branch around it.
 template <int K, int LOGV, typename T>
 __device__ __forceinline__ void bit_xz(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t c) {
-  const T f = c < 2u ? T(1) : T(0);
+  if (c >= 2u) return;
 #pragma unroll
   for (int i = 0; i < (1 << LOGV); ++i) {
     if (i & (1 << K)) continue;
     const int j = i | (1 << K);
-    const T ax = x[i], ay = y[i];
-    x[i] = fma(f, x[j], ax);
-    y[i] = fma(f, y[j], ay);
-    x[j] = fma(f, ax, -x[j]);
-    y[j] = fma(f, ay, -y[j]);
+    x[i] = x[i] + x[j];
+    y[i] = y[i] + y[j];
+    x[j] = fma(T(-2), x[j], x[i]);
+    y[j] = fma(T(-2), y[j], y[i]);
   }
 }
 
@@ -442,9 +350,11 @@ __device__ __forceinline__ void bstore2(double x, double y, rsrc_t rs, uint32_t 
 
 // BF16 storage of intermediate amplitudes: one complex number per 32-bit word,
 // real part in the low half, each rounded to nearest even (finite values).
-__device__ __forceinline__ uint32_t bf16_bits(float v) {
-  const uint32_t u = __float_as_uint(v);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pack(float x, float y) {
+  const f32x2_t v = {x, y};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 __device__ __forceinline__ void bload2h(float& x, float& y, rsrc_t rs, uint32_t voff, uint32_t soff) {
   const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0);
@@ -452,7 +362,7 @@ __device__ __forceinline__ void bload2h(float& x, float& y, rsrc_t rs, uint32_t 
   y = __uint_as_float(w & 0xffff0000u);
 }
 __device__ __forceinline__ void bstore2h(float x, float y, rsrc_t rs, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(bf16_bits(x) | (bf16_bits(y) << 16), rs, (int)voff, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(bf16_pack(x, y), rs, (int)voff, (int)soff, 0);
 }
 // Load or store a complex number kept in BF16 (H16) or in the working precision.
 template <bool H16, typename T>
