@@ -111,7 +111,16 @@ typedef enum {
  *             no loss is requested
  *   settings_per_batch  0: library default (or the autotuned value); otherwise the
  *             number of settings per batch of intermediate amplitudes (>= 1), which
- *             also keeps the instance out of multi-instance batches            */
+ *             also keeps the instance out of multi-instance batches
+ *   probs_base  NULL, or [B][D] base probabilities in the path's real type (float32;
+ *             float64 for QST_PATH_BUTTERFLY_F64), 4- (8-) byte aligned: the
+ *             instance then describes p = probs_base + sum_r alpha_r |V_b psi_r|^2
+ *             (a fixed part plus its atoms), and the loss, the sensitivities and
+ *             both gradients act on that p.  This is the response update of the
+ *             atom step (eq. pi-update): p_t as base, the old and the new atom
+ *             with weights -alpha_r and +alpha_r (see qst_atom_trial).  With
+ *             negative weights p may round below zero by about one ulp of
+ *             probs_base; eps of the cross-entropy should cover it.            */
 typedef struct {
   int32_t n_qubits;
   int32_t rank;
@@ -121,6 +130,7 @@ typedef struct {
   const double* weights;
   const uint8_t* settings;
   const float* freqs;
+  const void* probs_base;
 } qst_instance;
 
 typedef struct qst_handle qst_handle;
@@ -165,6 +175,27 @@ qst_status qst_forward(qst_handle* h, const qst_instance* inst, int n_inst, void
 qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, const void* const* grad_p,
                         void* const* atom_grad, double* const* weight_grad, double* loss,
                         qst_loss loss_kind, double eps, int project_tangent, qst_path path);
+
+/* Trial response of an atom step (update rules for the atom slots: eqs.
+ * atom-trial and pi-update).  With atom r of `inst` replaced by psi_trial,
+ *     p~ = p_t + alpha_r (a(psi_trial) - a(psi_r)),   a(psi)_{b,u} = |(V_b psi)_u|^2,
+ * and the loss at p~ -- what the acceptance rule (eq. state-acceptance-rule)
+ * compares -- without recomputing the other R-1 atoms.  The two one-atom
+ * responses run as one two-atom instance with weights (alpha_r, -alpha_r) on
+ * the base p_t: one pass at about 2/R of a full forward.
+ *   r            atom index, 0 <= r < rank
+ *   psi_trial    [D] complex64 (complex128 for F64) device vector, used as given
+ *   probs_t      [B][D] current probabilities (as written by qst_forward for this
+ *                instance; float32, float64 for F64), or NULL: p~ is then the
+ *                increment alpha_r (a(psi_trial) - a(psi_r)) alone
+ *   probs_trial  [B][D] output or NULL;  loss_trial: one float64 or NULL (needs freqs
+ *                and loss_kind != NONE).  inst->probs_base must be NULL.
+ * The pair of atoms and weights is staged in the handle's workspace by a copy
+ * kernel, so the call is capturable once the workspace fits.  Neither output may
+ * alias probs_t or the atoms. */
+qst_status qst_atom_trial(qst_handle* h, const qst_instance* inst, int r, const void* psi_trial,
+                          const void* probs_t, void* probs_trial, double* loss_trial, qst_loss loss_kind,
+                          double eps, qst_path path);
 
 /* Coefficient step with pruning (eqs. coefficient-update, truncation-map), FP64,
  * one work-group on the device (no allocation, capturable):

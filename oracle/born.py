@@ -11,6 +11,7 @@ Definitions followed (paper, problem-formulation and matrix-free sections):
 * weight gradient ``-A^T c``                                    (eq. weight-gradient)
 * atom Wirtinger gradient ``-alpha_r G psi_r``                  (eq. atom-wirtinger-gradient)
 * ``G = sum_m c_m E_m``                                         (eq. negative-gradient-matrix)
+* atom step: ``pi~ = pi + alpha_r (a(psi~_r) - a(psi_r))``        (eqs. atom-trial, pi-update)
 
 Interface convention (the paper stacks all settings into one POVM with the
 factor ``1/B`` inside ``E_{b,u}``):  arrays handed around here are *per
@@ -105,6 +106,23 @@ def probs_axis(atoms, weights, settings, rows=None) -> np.ndarray:
         phi = rotate_axis(atoms, settings[b])
         out.append(np.einsum("r,ru->u", w, np.abs(phi) ** 2))
     return np.asarray(out)
+
+
+# ---------------------------------------------------------------- atom step (response update)
+def atom_response_axis(psi, settings, rows=None) -> np.ndarray:
+    """One-atom response ``a(psi)[b, u] = |(V_b psi)_u|^2`` per setting (eq. atom-response in
+    the per-setting layout, i.e. ``B`` times the stacked ``a_m(psi)``)."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    return probs_axis(psi[None, :], np.ones(1), settings, rows)
+
+
+def atom_trial_probs(atoms, weights, settings, r, psi_trial, p_t, rows=None) -> np.ndarray:
+    """Probabilities after atom ``r`` is replaced by ``psi_trial`` (eq. atom-trial), by the
+    response update of eq. pi-update: ``p~ = p_t + alpha_r d`` with the response difference
+    ``d = a(psi_trial) - a(psi_r)``.  ``p_t`` holds the current probabilities of the rows used."""
+    alpha_r = float(np.asarray(weights, dtype=np.float64)[r])
+    d = atom_response_axis(psi_trial, settings, rows) - atom_response_axis(np.asarray(atoms)[r], settings, rows)
+    return np.asarray(p_t, dtype=np.float64) + alpha_r * d
 
 
 # ---------------------------------------------------------------- losses

@@ -25,7 +25,7 @@ LOSS_CE, LOSS_LS, LOSS_NONE = 0, 1, 2
 # Entry points declared in include/qst.h (checked against the header by the tests).
 EXPORTS = (
     "qst_create", "qst_destroy", "qst_set_stream", "qst_status_string", "qst_last_error", "qst_plan",
-    "qst_forward", "qst_backward", "qst_reweight_simplex", "qst_refactor", "qst_build_info",
+    "qst_forward", "qst_backward", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor", "qst_build_info",
     "qst_profile_enable", "qst_profile_read",
 )
 
@@ -40,6 +40,7 @@ class QstInstance(ctypes.Structure):
         ("weights", ctypes.c_void_p),
         ("settings", ctypes.c_void_p),
         ("freqs", ctypes.c_void_p),
+        ("probs_base", ctypes.c_void_p),
     ]
 
 
@@ -75,6 +76,8 @@ def load() -> ctypes.CDLL:
     lib.qst_forward.argtypes = [vp, P(QstInstance), ctypes.c_int, P(vp), vp, ctypes.c_int, dbl, ctypes.c_int]
     lib.qst_backward.argtypes = [vp, P(QstInstance), ctypes.c_int, P(vp), P(vp), P(vp), vp, ctypes.c_int, dbl,
                                  ctypes.c_int, ctypes.c_int]
+    lib.qst_atom_trial.argtypes = [vp, P(QstInstance), ctypes.c_int, vp, vp, vp, vp, ctypes.c_int, dbl,
+                                   ctypes.c_int]
     lib.qst_reweight_simplex.argtypes = [vp, vp, vp, ctypes.c_int, dbl, dbl, vp, vp, vp]
     lib.qst_refactor.argtypes = [vp, P(QstInstance), ctypes.c_int, dbl, dbl, dbl, dbl, ctypes.c_int, ctypes.c_int,
                                  vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]

@@ -17,7 +17,8 @@ from ._lib import (LOSS_CE, LOSS_LS, LOSS_NONE, PATH_AUTO, PATH_BUTTERFLY_BF16, 
                    PATH_BUTTERFLY_F64, PATH_PLAIN_F32, PATH_TILE_BF16, PATH_TILE_F16, QSTError, QstInstance)
 
 __all__ = [
-    "Handle", "Instance", "qst_forward", "qst_backward", "qst_reweight_simplex", "qst_refactor", "qst_plan",
+    "Handle", "Instance", "qst_forward", "qst_backward", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor",
+    "qst_plan",
     "LOSS_CE", "LOSS_LS", "LOSS_NONE", "PATH_AUTO", "PATH_BUTTERFLY_F32", "PATH_BUTTERFLY_F64", "PATH_PLAIN_F32",
     "PATH_TILE_F16", "PATH_TILE_BF16", "PATH_BUTTERFLY_BF16", "QSTError",
 ]
@@ -91,13 +92,15 @@ class Handle:
 @dataclass
 class Instance:
     """One tomography instance: atoms [R][D] complex, weights [R] float64,
-    settings [B][N] uint8 (X=0, Y=1, Z=2), freqs [B][D] float32 (optional)."""
+    settings [B][N] uint8 (X=0, Y=1, Z=2), freqs [B][D] float32 (optional),
+    probs_base [B][D] of the path's real type (optional: p = probs_base + the atoms' part)."""
 
     atoms: torch.Tensor
     weights: torch.Tensor
     settings: torch.Tensor
     freqs: Optional[torch.Tensor] = None
     settings_per_batch: int = 0  # 0: library default
+    probs_base: Optional[torch.Tensor] = None
 
     @property
     def shape(self):
@@ -120,9 +123,13 @@ class Instance:
             raise ValueError("atoms must be [R][2^N] and weights [R]")
         if self.freqs is not None and tuple(self.freqs.shape) != (B, 1 << N):
             raise ValueError("freqs must be [B][2^N]")
+        pb = self.probs_base
+        if pb is not None and (pb.dtype != _real_of(path) or not pb.is_contiguous() or tuple(pb.shape) != (B, 1 << N)):
+            raise ValueError("probs_base must be contiguous [B][2^N] of the path's real type")
         return QstInstance(N, R, B, int(self.settings_per_batch), self.atoms.data_ptr(), self.weights.data_ptr(),
                            self.settings.data_ptr(),
-                           None if self.freqs is None else self.freqs.data_ptr())
+                           None if self.freqs is None else self.freqs.data_ptr(),
+                           None if pb is None else pb.data_ptr())
 
 
 def _structs(insts: Sequence[Instance], path: int):
@@ -179,6 +186,25 @@ def qst_backward(h: Handle, insts: Sequence[Instance], grad_p: Optional[Sequence
     _lib.check(h.lib.qst_backward(h.h, arr, n, gpp, agp, wgp, _ptr(lt), loss, float(eps), int(project_tangent), path),
                h.h)
     return lt, ag, wg
+
+
+def qst_atom_trial(h: Handle, inst: Instance, r: int, psi_trial: torch.Tensor, probs_t: Optional[torch.Tensor],
+                   want_probs: bool = True, loss: int = LOSS_NONE, eps: float = 1e-8, path: int = PATH_AUTO):
+    """Response of the atom step: ``p~ = p_t + alpha_r (a(psi_trial) - a(psi_r))`` and the loss
+    at ``p~``.  Returns ``(probs [B][D] or None, loss [1] float64 or None)``."""
+    arr = _structs([inst], path)
+    N, R, B = inst.shape
+    dev = inst.atoms.device
+    if psi_trial.dtype != inst.atoms.dtype or not psi_trial.is_contiguous() or psi_trial.numel() != (1 << N):
+        raise ValueError("psi_trial must be a contiguous [D] vector of the atoms' dtype")
+    if probs_t is not None and (probs_t.dtype != _real_of(path) or not probs_t.is_contiguous()
+                                or tuple(probs_t.shape) != (B, 1 << N)):
+        raise ValueError("probs_t must be contiguous [B][D] of the path's real type")
+    out = torch.empty((B, 1 << N), dtype=_real_of(path), device=dev) if want_probs else None
+    lt = torch.empty(1, dtype=torch.float64, device=dev) if loss != LOSS_NONE else None
+    _lib.check(h.lib.qst_atom_trial(h.h, arr, int(r), _ptr(psi_trial), _ptr(probs_t), _ptr(out), _ptr(lt), loss,
+                                    float(eps), path), h.h)
+    return out, lt
 
 
 def qst_reweight_simplex(h: Handle, alpha: torch.Tensor, hvec: torch.Tensor, eta: float, tau: float):

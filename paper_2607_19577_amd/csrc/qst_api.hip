@@ -302,8 +302,9 @@ qst_status validate_instance(qst_handle* h, const qst_instance& in, qst_path pat
   if (!in.atoms || !in.weights || !in.settings) return set_err(h, QST_ERR_INVALID_ARG, "null atoms/weights/settings");
   if (need_freqs && !in.freqs) return set_err(h, QST_ERR_INVALID_ARG, "freqs required for the requested loss");
   const size_t ea = path == QST_PATH_BUTTERFLY_F64 ? 16 : 8;
-  if (!aligned(in.atoms, ea) || !aligned(in.weights, 8) || (in.freqs && !aligned(in.freqs, 4)))
-    return set_err(h, QST_ERR_ALIGN, "atoms/weights/freqs not aligned to their element size");
+  if (!aligned(in.atoms, ea) || !aligned(in.weights, 8) || (in.freqs && !aligned(in.freqs, 4)) ||
+      (in.probs_base && !aligned(in.probs_base, (size_t)elem_of(path))))
+    return set_err(h, QST_ERR_ALIGN, "atoms/weights/freqs/probs_base not aligned to their element size");
   return QST_OK;
 }
 
@@ -324,18 +325,23 @@ struct RunSpec {
   int S_override;
 };
 
+// Settings per batch of one instance: the override, else the caller's choice, the
+// autotuned value or the default, in that order.
+int batch_size(const qst_handle* h, const Geometry& g, const qst_instance& in, qst_path path, int S_override) {
+  if (S_override > 0) return std::min(S_override, g.B);
+  if (in.settings_per_batch > 0) return std::min((int)in.settings_per_batch, g.B);
+  auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)path));
+  if (it != h->tuned_S.end()) return std::min(it->second, g.B);
+  return default_S(g);
+}
+
 qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, size_t* ws_end = nullptr) {
   const qst_instance& in = *rs.in;
   const qst_path path = rs.path;
   Geometry g;
   qst_status st = make_geometry(h, in.n_qubits, in.rank, in.n_settings, path, g);
   if (st != QST_OK) return st;
-  int S = rs.S_override > 0 ? std::min(rs.S_override, g.B) : default_S(g);
-  if (rs.S_override <= 0) {
-    auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)path));
-    if (it != h->tuned_S.end()) S = std::min(it->second, g.B);
-    if (in.settings_per_batch > 0) S = std::min((int)in.settings_per_batch, g.B);
-  }
+  const int S = batch_size(h, g, in, path, rs.S_override);
   set_grid(h, g, S);
   const WsLayout L = layout_ws(g, S, path, false, ws_base);
   if (ws_end) *ws_end = L.total;
@@ -362,6 +368,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   la.freqs = in.freqs;
   la.grad_p = rs.grad_p;
   la.probs = rs.probs;
+  la.pbase = in.probs_base;
   la.gneg = rs.gneg;
   la.part = (want_loss || rs.adjoint) ? part : nullptr;
   la.nslots = nslots;
@@ -594,6 +601,7 @@ qst_status run_batch(qst_handle* h, const std::vector<const RunSpec*>& rs) {
     la.freqs = in.freqs;
     la.grad_p = r.grad_p;
     la.probs = r.probs;
+    la.pbase = in.probs_base;
     la.gneg = nullptr;
     la.part = (want_loss || adjoint) ? part : nullptr;
     la.nslots = L.g.grid_lo;
@@ -687,10 +695,7 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
       Geometry g;
       qst_status st = make_geometry(h, r->in->n_qubits, r->in->rank, r->in->n_settings, r->path, g);
       if (st != QST_OK) return st;
-      int S = default_S(g);
-      auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)r->path));
-      if (it != h->tuned_S.end()) S = std::min(it->second, g.B);
-      if (r->in->settings_per_batch > 0) S = std::min((int)r->in->settings_per_batch, g.B);
+      const int S = batch_size(h, g, *r->in, r->path, 0);
       set_grid(h, g, S);
       *need = std::max(*need, layout_ws(g, S, r->path, false).total);
       continue;
@@ -1070,6 +1075,69 @@ qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, con
     rs.adjoint = true;
   }
   st = run_call(h, specs);
+  if (st != QST_OK) return st;
+  post_flag(h);
+  return QST_OK;
+}
+
+qst_status qst_atom_trial(qst_handle* h, const qst_instance* inst, int r, const void* psi_trial,
+                          const void* probs_t, void* probs_trial, double* loss_trial, qst_loss loss_kind,
+                          double eps, qst_path path) {
+  qst_status st = common_checks(h, inst, 1, path);
+  if (st != QST_OK) return st;
+  path = resolve(path);
+  if (loss_kind < QST_LOSS_CE || loss_kind > QST_LOSS_NONE) return set_err(h, QST_ERR_INVALID_ARG, "bad loss kind");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return set_err(h, QST_ERR_INVALID_ARG, "eps must be finite and >= 0");
+  if (loss_trial && loss_kind == QST_LOSS_NONE)
+    return set_err(h, QST_ERR_INVALID_ARG, "loss requested with QST_LOSS_NONE");
+  st = validate_instance(h, *inst, path, loss_trial != nullptr);
+  if (st != QST_OK) return st;
+  if (inst->probs_base) return set_err(h, QST_ERR_INVALID_ARG, "probs_base must be NULL (probs_t is the base)");
+  if (r < 0 || r >= inst->rank) return set_err(h, QST_ERR_INVALID_ARG, "atom index out of range");
+  if (!psi_trial) return set_err(h, QST_ERR_INVALID_ARG, "null psi_trial");
+  const int elem = elem_of(path);
+  if (!aligned(psi_trial, 2 * (size_t)elem) || (probs_t && !aligned(probs_t, elem)) ||
+      (probs_trial && !aligned(probs_trial, elem)))
+    return set_err(h, QST_ERR_ALIGN, "psi_trial/probs_t/probs_trial not aligned to their element size");
+  if (probs_trial && (probs_trial == probs_t || probs_trial == inst->atoms))
+    return set_err(h, QST_ERR_INVALID_ARG, "probs_trial aliases probs_t or the atoms");
+  Geometry g;
+  st = make_geometry(h, inst->n_qubits, 2, inst->n_settings, path, g);
+  if (st != QST_OK) return st;
+  st = device_gate(h);
+  if (st != QST_OK) return st;
+
+  // The pair (psi_trial, psi_r) and its weights sit at the start of the workspace;
+  // the two-atom pass lays out its own buffers after them.  The workspace is sized
+  // for both before anything is enqueued, so no reallocation can drop the pair.
+  const size_t pair_bytes = al256((size_t)2 * g.D * 2 * elem);
+  const size_t base = al256(pair_bytes + 2 * sizeof(double));
+  qst_instance pair = *inst;
+  pair.rank = 2;
+  pair.probs_base = probs_t;
+  {
+    Geometry gp = g;
+    const int S = batch_size(h, gp, pair, path, 0);
+    set_grid(h, gp, S);
+    st = ensure_ws(h, layout_ws(gp, S, path, false, base).total);
+    if (st != QST_OK) return st;
+  }
+  unsigned char* ws = reinterpret_cast<unsigned char*>(h->ws);
+  double* wpair = reinterpret_cast<double*>(ws + pair_bytes);
+  pair.atoms = ws;
+  pair.weights = wpair;
+  prof_begin(h, PK_OTHER);
+  QST_HIP(qst::launch_atom_pair(elem, psi_trial, inst->atoms, inst->weights, r, g.D, ws, wpair, h->stream));
+  prof_end(h);
+  RunSpec rs{};
+  rs.in = &pair;
+  rs.path = path;
+  rs.loss_kind = loss_trial ? loss_kind : QST_LOSS_NONE;
+  rs.eps = eps;
+  rs.probs = probs_trial;
+  rs.loss = loss_trial;
+  rs.adjoint = false;
+  st = run_instance(h, rs, base);
   if (st != QST_OK) return st;
   post_flag(h);
   return QST_OK;

@@ -36,6 +36,7 @@ struct LoArgs {
   const float* freqs;         // [B][D] or null
   const void* grad_p;         // [B][D] or null (generic sensitivity)
   void* probs;                // [B][D] or null
+  const void* pbase;          // [B][D] or null: base probabilities added to p
   void* gneg;                 // [B][D] or null: receives -dL/dp
   double* part;               // [(R+1)][nslots]: row 0 loss, rows 1..R weight gradient
   long long nslots;
@@ -134,6 +135,10 @@ hipError_t launch_tangent(int elem, const void* atoms, void* grad, int R, long l
                           int g1, hipStream_t st);
 hipError_t launch_reweight(const double* alpha, const double* h, int R, double eta, double tau,
                            double* alpha_out, int32_t* keep, int32_t* R_out, hipStream_t st);
+
+// Stage the atom-step pair: pair [2][D] = (psi_trial, atoms[r]), wpair = (alpha_r, -alpha_r).
+hipError_t launch_atom_pair(int elem, const void* trial, const void* atoms, const double* alpha, int r, long long D,
+                            void* pair, double* wpair, hipStream_t st);
 
 // Plain per-qubit reference path (FP32).
 hipError_t launch_plain_copy(const void* atoms, void* X, int S, int R, long long D, hipStream_t st);

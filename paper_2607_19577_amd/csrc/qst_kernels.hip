@@ -532,6 +532,34 @@ hipError_t launch_reweight(const double* alpha, const double* h, int R, double e
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ atom-step pair (eq. pi-update)
+// pair[0] = psi_trial, pair[1] = atoms[r]; wpair = (alpha_r, -alpha_r).  Elements are
+// copied as 8-byte words (elem_words per complex: 1 for complex64, 2 for complex128).
+__global__ void k_atom_pair(const unsigned long long* __restrict__ trial, const unsigned long long* __restrict__ atoms,
+                            const double* __restrict__ alpha, int r, long long words,
+                            unsigned long long* __restrict__ pair, double* __restrict__ wpair) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < words; e += stride) {
+    pair[e] = trial[e];
+    pair[words + e] = atoms[(long long)r * words + e];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    wpair[0] = alpha[r];
+    wpair[1] = -alpha[r];
+  }
+}
+
+hipError_t launch_atom_pair(int elem, const void* trial, const void* atoms, const double* alpha, int r, long long D,
+                            void* pair, double* wpair, hipStream_t st) {
+  const long long words = D * (elem == 8 ? 2 : 1);
+  long long nb = (words + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  k_atom_pair<<<(unsigned)nb, 256, 0, st>>>(reinterpret_cast<const unsigned long long*>(trial),
+                                           reinterpret_cast<const unsigned long long*>(atoms), alpha, r, words,
+                                           reinterpret_cast<unsigned long long*>(pair), wpair);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ plain per-qubit reference path (FP32)
 __global__ void k_plain_copy(const float2* __restrict__ psi, float2* __restrict__ X, int S, long long RD) {
   const long long n = (long long)S * RD;
@@ -613,6 +641,7 @@ __global__ __launch_bounds__(256) void k_plain_point(const LoArgs a, float2* __r
     }
     p *= s2;
     const long long gi = (long long)b * D + u;
+    if (a.pbase) p += reinterpret_cast<const float*>(a.pbase)[gi];
     if (a.probs) reinterpret_cast<float*>(a.probs)[gi] = p;
     if (a.grad_p) {
       g = reinterpret_cast<const float*>(a.grad_p)[gi];

@@ -298,6 +298,7 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
       T p = 0;
       for (int r = 0; r < a.R; ++r) p += qb[(size_t)r * UPAD + pad32(u)];
       p *= s2;
+      if (a.pbase) p += reinterpret_cast<const T*>(a.pbase)[row + u];
       if (a.probs) reinterpret_cast<T*>(a.probs)[row + u] = p;
       T d = 0;  // the data value of this outcome: dL/dp (generic) or the frequency
       if (row_data) {
