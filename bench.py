@@ -321,6 +321,27 @@ def main():
             tms = (time.perf_counter() - t0) * 1e3
             extras[f"{name}_path_ms"] = round(tms, 1)
             extras[f"{name}_speedup_vs_plain"] = round(plain_ms / tms, 2)
+        # atom step (eq. pi-update): response of one replaced atom on top of p_t, with the loss,
+        # against the full forward (probabilities and loss of all R atoms)
+        def med3(fn):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return sorted(ts)[1]
+
+        p_t, _ = api.qst_forward(h, [inst], want_probs=True, loss=api.LOSS_CE, eps=1e-8)
+        trial = torch.from_numpy(synth.haar_atoms(synth.make_rng(seed + 13), 1, D, dtype=np.complex64)[0]).to(dev)
+        fwd_ms = med3(lambda: api.qst_forward(h, [inst], want_probs=True, loss=api.LOSS_CE, eps=1e-8))
+        trial_ms = med3(lambda: api.qst_atom_trial(h, inst, R // 2, trial, p_t[0], loss=api.LOSS_CE, eps=1e-8))
+        del p_t
+        extras["forward_probs_loss_ms"] = round(fwd_ms, 1)
+        extras["atom_trial_ms"] = round(trial_ms, 1)
+        extras["atom_trial_speedup_vs_forward"] = round(fwd_ms / trial_ms, 2)
         v0 = torch.from_numpy(synth.haar_atoms(synth.make_rng(seed + 11), 1, D)[0]).to(dev)
         t0 = time.perf_counter()
         res = api.qst_refactor(h, inst, api.LOSS_CE, 1e-8, 0.5, 1e-3, 1e-3, 8, 30, v0)
