@@ -294,24 +294,18 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
     for (int i = 0; i < V; ++i) qrow[pad_off<0>(i)] = al * fma(x[i], x[i], y[i] * y[i]);
     __syncthreads();
     const long long row = (long long)b * D + ((long long)h << N_LO);
-    for (int j = 0, u = tid; u < U; ++j, u += nthr) {
+    const T* gp = reinterpret_cast<const T*>(a.grad_p);
+    const T* pbp = reinterpret_cast<const T*>(a.pbase);
+    // One outcome u of the chunk: p (atom sum, scale, base), loss term, sensitivity.
+    // d is the data value of the outcome (dL/dp in the generic mode, else the frequency).
+    auto outcome = [&](int u, T d, T pb) __attribute__((always_inline)) {
       T p = 0;
       for (int r = 0; r < a.R; ++r) p += qb[(size_t)r * UPAD + pad32(u)];
       p *= s2;
-      if (a.pbase) p += reinterpret_cast<const T*>(a.pbase)[row + u];
+      if (pbp) p += pb;
       if (a.probs) reinterpret_cast<T*>(a.probs)[row + u] = p;
-      T d = 0;  // the data value of this outcome: dL/dp (generic) or the frequency
-      if (row_data) {
-        if (j < NPF) {
-#pragma unroll
-          for (int jj = 0; jj < NPF; ++jj)
-            if (jj == j) d = fv[jj];
-        } else {
-          d = a.grad_p ? reinterpret_cast<const T*>(a.grad_p)[row + u] : (T)a.freqs[row + u];
-        }
-      }
       T g = 0;
-      if (a.grad_p) {
+      if (gp) {
         g = d;
       } else if constexpr (std::is_same<T, float>::value) {
         // FP32 path: p carries single-precision rounding already, so each term is
@@ -342,6 +336,33 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
       }
       if (a.gneg) reinterpret_cast<T*>(a.gneg)[row + u] = -g;
       if (ADJ) gb[pad32(u)] = g * s2;
+    };
+    // This thread's outcomes are u = tid + j * nthr.  The first NPF data values were
+    // prefetched with the chunk; the rest (and the base values) are loaded in groups of
+    // NG whose loads are all in flight before the first of them is used.
+    constexpr int NG = 4;
+    for (int j0 = 0; tid + j0 * nthr < U; j0 += NG) {
+      T dg[NG], bg[NG];
+#pragma unroll
+      for (int jj = 0; jj < NG; ++jj) {
+        const int u = tid + (j0 + jj) * nthr;
+        dg[jj] = 0;
+        bg[jj] = 0;
+        if (u < U) {
+          if (row_data) {
+            if (jj < NPF && j0 == 0)
+              dg[jj] = fv[jj < NPF ? jj : 0];
+            else
+              dg[jj] = gp ? gp[row + u] : (T)a.freqs[row + u];
+          }
+          if (pbp) bg[jj] = pbp[row + u];
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < NG; ++jj) {
+        const int u = tid + (j0 + jj) * nthr;
+        if (u < U) outcome(u, dg[jj], bg[jj]);
+      }
     }
     __syncthreads();
     if (ADJ) {
