@@ -228,6 +228,67 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
                         void* atoms_out, double* weights_out, int32_t* R_out, int32_t* s_star,
                         double* ritz_vals, double* ritz_resid, double* q_scores, qst_path path);
 
+/* Parameters of the rank-adaptive iteration (Algorithm 1); the defaults of Table
+ * sim-parameters in brackets. */
+typedef struct {
+  int32_t max_slots;     /* T: slots t = 0..T-1                                            */
+  int32_t t_alpha;       /* [5]  coefficient slot when t % t_alpha == 0 (0: never)           */
+  int32_t t_ref;         /* [50] spectral slot when t % t_ref == 0, tested first (0: never)  */
+  int32_t n_grid;        /* [11] step grid {2^-j}, j = 0..n_grid-1, tried largest first     */
+  int32_t rank_max;      /* [8]  R_max: capacity of the state and L of the Ritz step        */
+  int32_t n_lanczos;     /* [30] Lanczos steps per spectral trial                           */
+  int32_t stop_window;   /* [20] accepted updates over which delta is measured (0: off)     */
+  int32_t loss_kind;     /* QST_LOSS_CE [paper] or QST_LOSS_LS                              */
+  double stop_delta;     /* [1e-4] stop once the relative decrease over the window is below */
+  double mu;             /* [1e-3] rank penalty of J = L + mu R (eq. fixed-rank-objective)   */
+  double eps;            /* [1e-8] */
+  double tau;            /* [1e-3] pruning threshold (eq. truncation-map)                   */
+  double tau_acc;        /* [1e-10] acceptance margin (eq. state-acceptance-rule)           */
+  int64_t oracle_budget; /* [1e5] stop once the oracle-call count reaches it (0: off)       */
+} qst_solve_params;
+
+/* The rank-adaptive iteration (Algorithm 1) on one instance, driven from the host
+ * with every oracle call on the device:
+ *   slot t: spectral when t % t_ref == 0 (eqs. density-proposal .. spectral-selection,
+ *   through qst_refactor), else coefficient when t % t_alpha == 0 (eq.
+ *   coefficient-update and the pruning map, qst_reweight_simplex), else an atom step
+ *   on atom r_t = t mod R_t (eqs. atom-direction, atom-trial; the response by eq.
+ *   pi-update, qst_atom_trial).  Each trial takes the step sizes of the grid from
+ *   the largest down and the first that satisfies the acceptance rule (eq.
+ *   state-acceptance-rule, J = L + mu R) is kept; otherwise the state stays.
+ *   Stopping (Table sim-parameters): max_slots, the relative decrease of J over the
+ *   last stop_window accepted updates below stop_delta, or the oracle budget.  One
+ *   oracle call is counted per gradient product (G psi_r or A^T c), per trial
+ *   response with its loss, and per Lanczos product G v (n_lanczos, at most D, per
+ *   spectral trial).
+ *   inst         the initial state X_0 (rank R_0 <= rank_max, unit atoms), settings
+ *                and freqs (required); probs_base must be NULL
+ *   v0s          [n_v0][D] complex128 device: Lanczos start vectors, spectral slot k
+ *                uses v0s[k mod n_v0] (the random draws are inputs); may be NULL
+ *                when t_ref == 0
+ *   atoms_out    [rank_max][D] complex64 (complex128 for F64), device: the final
+ *                atoms, zero rows beyond the final rank; weights_out [rank_max]
+ *                float64, device (zeros beyond);  rank_out: HOST int32
+ *   history      HOST [max_slots][6] float64 or NULL: per slot run (t, kind 0 spectral
+ *                / 1 coefficient / 2 atom, J after the slot, R after, accepted 0/1,
+ *                accepted grid index or -1)
+ *   info         HOST int64[3] or NULL: slots run, oracle calls, stop reason (0 slots,
+ *                1 delta, 2 budget)
+ * Synchronises the stream (the acceptance tests read scalars), allocates its own
+ * scratch (two [B][D] probability arrays, two state copies) and is not capturable. */
+qst_status qst_solve(qst_handle* h, const qst_instance* inst, const qst_solve_params* prm, const void* v0s,
+                     int n_v0, void* atoms_out, double* weights_out, int32_t* rank_out, double* history,
+                     int64_t* info, qst_path path);
+
+/* Relative Frobenius distance e = ||rho_a - rho_b||_F / ||rho_b||_F of two atomic
+ * states (the error metric of the numerical-test section), in Gram form without
+ * dense matrices: ||sum_r a_r |u_r><u_r| ||_F^2 = sum_{r,r'} a_r a_r' |<u_r|u_r'>|^2,
+ * and likewise for the cross term.  atoms_a [R_a][D], atoms_b [R_b][D] complex64
+ * (complex128 for F64) and weights float64 on the device; *out on the HOST.
+ * Synchronises; allocates scratch of (R_a + R_b) complex128 rows. */
+qst_status qst_state_error(qst_handle* h, int n_qubits, const void* atoms_a, const double* w_a, int R_a,
+                           const void* atoms_b, const double* w_b, int R_b, double* out, qst_path path);
+
 /* Per-stage timing of the hot path (measurement support; not needed for results).
  * qst_profile_enable(h, 1) brackets every kernel launch the handle makes with a pair
  * of HIP events on its stream, grouped by stage kind:

@@ -125,6 +125,23 @@ def atom_trial_probs(atoms, weights, settings, r, psi_trial, p_t, rows=None) -> 
     return np.asarray(p_t, dtype=np.float64) + alpha_r * d
 
 
+def state_error(atoms_a, w_a, atoms_b, w_b) -> float:
+    """Relative Frobenius error ``||rho_a - rho_b||_F / ||rho_b||_F`` (the error metric of the
+    numerical-test section) from Gram matrices of the atoms, without dense densities:
+    ``||sum_r a_r |u_r><u_r| ||_F^2 = sum_{r,r'} a_r a_r' |<u_r|u_r'>|^2``, and the cross term
+    likewise."""
+    ua = np.asarray(atoms_a, dtype=np.complex128)
+    ub = np.asarray(atoms_b, dtype=np.complex128)
+    wa = np.asarray(w_a, dtype=np.float64)
+    wb = np.asarray(w_b, dtype=np.float64)
+
+    def gram(u, a, v, b):
+        return float(a @ (np.abs(u.conj() @ v.T) ** 2) @ b)
+
+    aa, ab, bb = gram(ua, wa, ua, wa), gram(ua, wa, ub, wb), gram(ub, wb, ub, wb)
+    return math.sqrt(max(aa - 2.0 * ab + bb, 0.0) / bb)
+
+
 # ---------------------------------------------------------------- losses
 def _sum(x: np.ndarray) -> float:
     x = np.asarray(x, dtype=np.float64).reshape(-1)

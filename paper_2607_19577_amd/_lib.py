@@ -25,8 +25,8 @@ LOSS_CE, LOSS_LS, LOSS_NONE = 0, 1, 2
 # Entry points declared in include/qst.h (checked against the header by the tests).
 EXPORTS = (
     "qst_create", "qst_destroy", "qst_set_stream", "qst_status_string", "qst_last_error", "qst_plan",
-    "qst_forward", "qst_backward", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor", "qst_build_info",
-    "qst_profile_enable", "qst_profile_read",
+    "qst_forward", "qst_backward", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor", "qst_solve",
+    "qst_state_error", "qst_build_info", "qst_profile_enable", "qst_profile_read",
 )
 
 
@@ -41,6 +41,25 @@ class QstInstance(ctypes.Structure):
         ("settings", ctypes.c_void_p),
         ("freqs", ctypes.c_void_p),
         ("probs_base", ctypes.c_void_p),
+    ]
+
+
+class QstSolveParams(ctypes.Structure):
+    _fields_ = [
+        ("max_slots", ctypes.c_int32),
+        ("t_alpha", ctypes.c_int32),
+        ("t_ref", ctypes.c_int32),
+        ("n_grid", ctypes.c_int32),
+        ("rank_max", ctypes.c_int32),
+        ("n_lanczos", ctypes.c_int32),
+        ("stop_window", ctypes.c_int32),
+        ("loss_kind", ctypes.c_int32),
+        ("stop_delta", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("tau_acc", ctypes.c_double),
+        ("oracle_budget", ctypes.c_int64),
     ]
 
 
@@ -81,6 +100,9 @@ def load() -> ctypes.CDLL:
     lib.qst_reweight_simplex.argtypes = [vp, vp, vp, ctypes.c_int, dbl, dbl, vp, vp, vp]
     lib.qst_refactor.argtypes = [vp, P(QstInstance), ctypes.c_int, dbl, dbl, dbl, dbl, ctypes.c_int, ctypes.c_int,
                                  vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
+    lib.qst_solve.argtypes = [vp, P(QstInstance), P(QstSolveParams), vp, ctypes.c_int, vp, vp, P(i32), vp, vp,
+                              ctypes.c_int]
+    lib.qst_state_error.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(dbl), ctypes.c_int]
     lib.qst_profile_enable.argtypes = [vp, ctypes.c_int]
     lib.qst_profile_read.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(dbl), ctypes.c_int]
     for name in EXPORTS:

@@ -14,11 +14,12 @@ import torch
 
 from . import _lib
 from ._lib import (LOSS_CE, LOSS_LS, LOSS_NONE, PATH_AUTO, PATH_BUTTERFLY_BF16, PATH_BUTTERFLY_F32,
-                   PATH_BUTTERFLY_F64, PATH_PLAIN_F32, PATH_TILE_BF16, PATH_TILE_F16, QSTError, QstInstance)
+                   PATH_BUTTERFLY_F64, PATH_PLAIN_F32, PATH_TILE_BF16, PATH_TILE_F16, QSTError, QstInstance,
+                   QstSolveParams)
 
 __all__ = [
     "Handle", "Instance", "qst_forward", "qst_backward", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor",
-    "qst_plan",
+    "qst_plan", "qst_solve", "qst_state_error", "SolveParams",
     "LOSS_CE", "LOSS_LS", "LOSS_NONE", "PATH_AUTO", "PATH_BUTTERFLY_F32", "PATH_BUTTERFLY_F64", "PATH_PLAIN_F32",
     "PATH_TILE_F16", "PATH_TILE_BF16", "PATH_BUTTERFLY_BF16", "QSTError",
 ]
@@ -235,3 +236,74 @@ def qst_refactor(h: Handle, inst: Instance, loss: int, eps: float, eta_rho: floa
                                   int(n_lanczos), _ptr(v0), _ptr(atoms_out), _ptr(w_out), _ptr(r_out), _ptr(s_star),
                                   _ptr(rv), _ptr(rr), _ptr(qs), path), h.h)
     return dict(atoms=atoms_out, weights=w_out, R=r_out, s_star=s_star, ritz_vals=rv, ritz_resid=rr, q_scores=qs)
+
+
+@dataclass
+class SolveParams:
+    """Parameters of the rank-adaptive iteration; defaults of the paper's Table sim-parameters."""
+
+    max_slots: int = 1000
+    t_alpha: int = 5
+    t_ref: int = 50
+    n_grid: int = 11
+    rank_max: int = 8
+    n_lanczos: int = 30
+    stop_window: int = 20
+    loss_kind: int = LOSS_CE
+    stop_delta: float = 1e-4
+    mu: float = 1e-3
+    eps: float = 1e-8
+    tau: float = 1e-3
+    tau_acc: float = 1e-10
+    oracle_budget: int = 100_000
+
+    def c_struct(self) -> QstSolveParams:
+        return QstSolveParams(self.max_slots, self.t_alpha, self.t_ref, self.n_grid, self.rank_max, self.n_lanczos,
+                              self.stop_window, self.loss_kind, self.stop_delta, self.mu, self.eps, self.tau,
+                              self.tau_acc, self.oracle_budget)
+
+
+def qst_solve(h: Handle, inst: Instance, params: SolveParams, v0s: Optional[torch.Tensor] = None,
+              path: int = PATH_AUTO) -> dict:
+    """Rank-adaptive iteration from the state in ``inst``.  ``v0s`` [n_v0][D] complex128 holds the Lanczos
+    start vectors.  Returns a dict: atoms [R][D], weights [R], rank, history [slots][6] (numpy), slots,
+    oracle_calls, stopped ('slots', 'delta' or 'budget')."""
+    import numpy as np
+
+    arr = _structs([inst], path)
+    N, R, B = inst.shape
+    dev = inst.atoms.device
+    if v0s is not None and (v0s.dtype != torch.complex128 or not v0s.is_contiguous() or v0s.dim() != 2
+                            or v0s.shape[1] != (1 << N)):
+        raise ValueError("v0s must be contiguous [n_v0][D] complex128")
+    cap = params.rank_max
+    atoms = torch.zeros((cap, 1 << N), dtype=inst.atoms.dtype, device=dev)
+    w = torch.zeros(cap, dtype=torch.float64, device=dev)
+    rank = ctypes.c_int32(0)
+    hist = np.zeros((max(params.max_slots, 1), 6), dtype=np.float64)
+    info = np.zeros(3, dtype=np.int64)
+    prm = params.c_struct()
+    n_v0 = 0 if v0s is None else int(v0s.shape[0])
+    _lib.check(h.lib.qst_solve(h.h, arr, ctypes.byref(prm), _ptr(v0s), n_v0, _ptr(atoms), _ptr(w),
+                               ctypes.byref(rank), hist.ctypes.data_as(ctypes.c_void_p),
+                               info.ctypes.data_as(ctypes.c_void_p), path), h.h)
+    Rf = int(rank.value)
+    slots = int(info[0])
+    return dict(atoms=atoms[:Rf], weights=w[:Rf], rank=Rf, history=hist[:slots], slots=slots,
+                oracle_calls=int(info[1]), stopped=("slots", "delta", "budget")[int(info[2])])
+
+
+def qst_state_error(h: Handle, atoms_a: torch.Tensor, w_a: torch.Tensor, atoms_b: torch.Tensor, w_b: torch.Tensor,
+                    path: int = PATH_AUTO) -> float:
+    """``||rho_a - rho_b||_F / ||rho_b||_F`` of two atomic states (Gram form, on the device)."""
+    D = atoms_a.shape[1]
+    n = D.bit_length() - 1
+    for t in (atoms_a, w_a, atoms_b, w_b):
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+    if atoms_a.dtype != _C_OF_PATH[path] or atoms_b.dtype != _C_OF_PATH[path] or atoms_b.shape[1] != D:
+        raise ValueError("atoms must be [R][D] of the path's complex type")
+    out = ctypes.c_double(0.0)
+    _lib.check(h.lib.qst_state_error(h.h, n, _ptr(atoms_a), _ptr(w_a), atoms_a.shape[0], _ptr(atoms_b), _ptr(w_b),
+                                     atoms_b.shape[0], ctypes.byref(out), path), h.h)
+    return float(out.value)

@@ -767,6 +767,12 @@ std::vector<double> proj_simplex(const std::vector<double>& v) {
 
 }  // namespace
 
+// Internal access for the host-orchestrated iteration (qst_solve.hip); not exported.
+#define QST_HIDDEN __attribute__((visibility("hidden")))
+QST_HIDDEN hipStream_t qst_host_stream(qst_handle* h) { return h->stream; }
+QST_HIDDEN qst_status qst_host_error(qst_handle* h, qst_status s, const std::string& msg) { return set_err(h, s, msg); }
+QST_HIDDEN int qst_host_device(const qst_handle* h) { return h->device; }
+
 // ==================================================================== C ABI
 extern "C" {
 

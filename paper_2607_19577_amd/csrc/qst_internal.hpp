@@ -140,6 +140,14 @@ hipError_t launch_reweight(const double* alpha, const double* h, int R, double e
 hipError_t launch_atom_pair(int elem, const void* trial, const void* atoms, const double* alpha, int r, long long D,
                             void* pair, double* wpair, hipStream_t st);
 
+// Iteration helpers: the normalised trial atom (psi + eta d) / ||psi + eta d|| (part: kTrialBlocks
+// doubles, lvl1: g1 doubles, sumsq: one double), and a row gather with zero fill.
+constexpr int kTrialBlocks = 1024;
+hipError_t launch_trial_atom(int elem, const void* psi, const void* d, double eta, void* y, long long D,
+                             double* part, double* lvl1, int g1, double* sumsq, hipStream_t st);
+hipError_t launch_gather_rows(int elem, const void* src, const int32_t* idx, const int32_t* count, int rows_max,
+                              long long D, void* dst, hipStream_t st);
+
 // Plain per-qubit reference path (FP32).
 hipError_t launch_plain_copy(const void* atoms, void* X, int S, int R, long long D, hipStream_t st);
 hipError_t launch_plain_qubit(void* X, int S, int R, long long D, int bit, const uint64_t* pc, int b0, bool adj,

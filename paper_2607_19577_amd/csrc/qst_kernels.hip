@@ -814,4 +814,84 @@ hipError_t launch_axpy_c(void* y, int y_c64, const void* x, int x_c64, long long
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ iteration helpers (Algorithm 1)
+// Trial atom of eq. atom-trial: y = psi + eta * d, then y / ||y||.  Pass 1 writes y and
+// per-block FP64 partials of |y|^2 (fixed grid, fixed order); the partials are summed by
+// the two-level row sum; pass 2 scales by 1/sqrt(sum).
+template <typename C>
+__global__ __launch_bounds__(256) void k_trial_axpy(const C* __restrict__ psi, const C* __restrict__ d, double eta,
+                                                    C* __restrict__ y, long long D, double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < D; i += (long long)gridDim.x * 256) {
+    const double2 a = ld_c<C>(psi, i);
+    const double2 b = ld_c<C>(d, i);
+    C v;
+    v.x = (decltype(v.x))fma(eta, b.x, a.x);
+    v.y = (decltype(v.y))fma(eta, b.y, a.y);
+    y[i] = v;
+    acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+  }
+  const double r = block_tree(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+template <typename C>
+__global__ void k_scale_rsqrt(C* __restrict__ y, long long D, const double* __restrict__ sumsq) {
+  const double sc = 1.0 / sqrt(*sumsq);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < D; i += (long long)gridDim.x * blockDim.x) {
+    C v = y[i];
+    v.x = (decltype(v.x))((double)v.x * sc);
+    v.y = (decltype(v.y))((double)v.y * sc);
+    y[i] = v;
+  }
+}
+
+hipError_t launch_trial_atom(int elem, const void* psi, const void* d, double eta, void* y, long long D,
+                             double* part, double* lvl1, int g1, double* sumsq, hipStream_t st) {
+  const int nb = kTrialBlocks;
+  if (elem == 8)
+    k_trial_axpy<double2><<<nb, 256, 0, st>>>(reinterpret_cast<const double2*>(psi),
+                                             reinterpret_cast<const double2*>(d), eta,
+                                             reinterpret_cast<double2*>(y), D, part);
+  else
+    k_trial_axpy<float2><<<nb, 256, 0, st>>>(reinterpret_cast<const float2*>(psi),
+                                            reinterpret_cast<const float2*>(d), eta, reinterpret_cast<float2*>(y),
+                                            D, part);
+  hipError_t e = launch_rowsum(part, 1, nb, lvl1, g1, sumsq, st);
+  if (e != hipSuccess) return e;
+  long long sb = (D + 255) / 256;
+  if (sb > 4096) sb = 4096;
+  if (elem == 8)
+    k_scale_rsqrt<double2><<<(unsigned)sb, 256, 0, st>>>(reinterpret_cast<double2*>(y), D, sumsq);
+  else
+    k_scale_rsqrt<float2><<<(unsigned)sb, 256, 0, st>>>(reinterpret_cast<float2*>(y), D, sumsq);
+  return hipGetLastError();
+}
+
+// dst row i = src row idx[i] for i < *count (rows of `words` 8-byte words); rows from
+// *count to rows_max are zeroed.
+__global__ void k_gather_rows(const unsigned long long* __restrict__ src, const int32_t* __restrict__ idx,
+                              const int32_t* __restrict__ count, int rows_max, long long words,
+                              unsigned long long* __restrict__ dst) {
+  const int row = blockIdx.y;
+  if (row >= rows_max) return;
+  const int n = *count;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < words; e += stride)
+    dst[(long long)row * words + e] = row < n ? src[(long long)idx[row] * words + e] : 0ull;
+}
+
+hipError_t launch_gather_rows(int elem, const void* src, const int32_t* idx, const int32_t* count, int rows_max,
+                              long long D, void* dst, hipStream_t st) {
+  if (rows_max < 1) return hipSuccess;
+  const long long words = D * (elem == 8 ? 2 : 1);
+  long long nb = (words + 255) / 256;
+  if (nb > 2048) nb = 2048;
+  k_gather_rows<<<dim3((unsigned)nb, (unsigned)rows_max), 256, 0, st>>>(
+      reinterpret_cast<const unsigned long long*>(src), idx, count, rows_max, words,
+      reinterpret_cast<unsigned long long*>(dst));
+  return hipGetLastError();
+}
+
 }  // namespace qst

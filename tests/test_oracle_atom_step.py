@@ -86,3 +86,19 @@ def test_update_is_linear_in_the_weight():
     rep[1] = trial
     back = born.atom_trial_probs(rep, w, s, 1, atoms[1], p_t) - p_t
     assert np.allclose(back, -d1, atol=1e-14)
+
+
+def test_state_error_gram_form_matches_dense():
+    # the Gram form against dense densities and the Frobenius norm (numpy), plus closed forms
+    rng = synth.make_rng(150)
+    for n, Ra, Rb in ((3, 2, 3), (5, 4, 1), (6, 1, 1)):
+        ua = synth.haar_atoms(rng, Ra, 1 << n)
+        ub = synth.haar_atoms(rng, Rb, 1 << n)
+        wa = synth.dirichlet_weights(rng, Ra)
+        wb = synth.dirichlet_weights(rng, Rb)
+        ra, rb = born.density(ua, wa), born.density(ub, wb)
+        want = np.linalg.norm(ra - rb) / np.linalg.norm(rb)
+        assert abs(born.state_error(ua, wa, ub, wb) - want) < 1e-12
+        assert born.state_error(ua, wa, ua, wa) < 1e-7
+    e0 = np.eye(4, dtype=np.complex128)
+    assert abs(born.state_error(e0[:1], [1.0], e0[1:2], [1.0]) - np.sqrt(2.0)) < 1e-15  # orthogonal pure states
