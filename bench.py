@@ -122,6 +122,44 @@ def read_traffic(kernel_kind: str, workload: str):
     return float(d["bytes_per_launch"])
 
 
+def solve_extra(api, h, dev, seed: int, slots: int = 100):
+    """The rank-adaptive iteration (Algorithm 1) on the n=14, R_max=8, B=1000 workload: truth of
+    rank 4, frequencies Poisson(1e5 p)/1e5 from the library's own forward of the truth, start
+    R_0 = R_max with alpha_0 = 1/R_max, coefficient slots every 5 and spectral slots every 10.
+    Wall time of the bounded run, slots, final rank, objective and error e_rho against the truth."""
+    import torch
+
+    wl = WORKLOADS["n14_r8_b1000"]
+    n, Rmax, B, shots = wl["n"], wl["R"], wl["B"], wl["shots"]
+    D = 1 << n
+    rng = synth.make_rng(seed)
+    s = torch.from_numpy(synth.random_settings(rng, B, n)).to(dev)
+    truth = torch.from_numpy(synth.haar_atoms(rng, wl["R_true"], D, dtype=np.complex64)).to(dev)
+    wt = torch.from_numpy(synth.dirichlet_weights(rng, wl["R_true"])).to(dev)
+    p_true, _ = api.qst_forward(h, [api.Instance(truth, wt, s)], want_probs=True)
+    f = synth.poisson_freqs_torch(seed + 1, p_true[0], shots)
+    del p_true
+    atoms0 = torch.from_numpy(synth.haar_atoms(rng, Rmax, D, dtype=np.complex64)).to(dev)
+    w0 = torch.full((Rmax,), 1.0 / Rmax, dtype=torch.float64, device=dev)
+    v0s = torch.from_numpy(synth.haar_atoms(rng, 4, D, dtype=np.complex128)).to(dev)
+    inst = api.Instance(atoms0, w0, s, f)
+    prm = api.SolveParams(max_slots=slots, t_alpha=5, t_ref=10, rank_max=Rmax, n_lanczos=30)
+    e0 = api.qst_state_error(h, atoms0, w0, truth, wt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = api.qst_solve(h, inst, prm, v0s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e1 = api.qst_state_error(h, res["atoms"].contiguous(), res["weights"].contiguous(), truth, wt)
+    hist = res["history"]
+    return {"workload": "n=14, R_max=8, B=1000, 1e5 shots, truth rank 4; t_alpha=5, t_ref=10, grid 2^-j (11)",
+            "slots": res["slots"], "stopped": res["stopped"], "wall_s": round(dt, 2),
+            "ms_per_slot": round(dt * 1e3 / max(res["slots"], 1), 2), "accepted": int(hist[:, 4].sum()),
+            "oracle_calls": res["oracle_calls"], "rank_final": res["rank"],
+            "J_first_slot": round(float(hist[0, 2]), 6), "J_final": round(float(hist[-1, 2]), 6),
+            "e_rho_initial": round(e0, 4), "e_rho_final": round(e1, 4)}
+
+
 def uneven_batch_extra(api, h, dev, seed: int, reps: int = 5):
     """64 independent instances, n in 6..12, R in 1..8, B in 50..500 (fused CE backward with the
     tangent projection): one call (batched launches), the same call replayed from a graph, and
@@ -351,6 +389,7 @@ def main():
 
     if not args.no_extras:
         extras["uneven64"] = uneven_batch_extra(api, h, dev, seed + 21)
+        extras["solve"] = solve_extra(api, h, dev, seed + 31)
 
     out = {
         "metric": "fwd+adjoint atom-setting amplitudes/s",

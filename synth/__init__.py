@@ -116,6 +116,17 @@ def porter_thomas_freqs_torch(seed: int, B: int, D: int, weights, shots: int, de
     return out
 
 
+def poisson_freqs_torch(seed: int, probs, shots: int):
+    """Frequencies ``Poisson(shots * p) / shots`` of given per-setting probabilities ``probs``
+    (a device tensor ``[B][D]``), drawn with torch's seeded generator on the same device: the
+    large-count stand-in for multinomial sampling where ``B*D`` is large."""
+    import torch
+
+    gen = torch.Generator(device=probs.device)
+    gen.manual_seed(int(seed))
+    return (torch.poisson(probs.float().clamp_min(0.0) * float(shots), generator=gen) / float(shots)).float()
+
+
 # Workload shapes (number of qubits, atoms, settings, shots) used by tests and the benchmark.
 WORKLOADS = {
     "n4_r2_all81": dict(n=4, R=2, B=81, shots=1000, R_true=2, exhaustive=True),
