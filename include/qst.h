@@ -120,7 +120,17 @@ typedef enum {
  *             atom step (eq. pi-update): p_t as base, the old and the new atom
  *             with weights -alpha_r and +alpha_r (see qst_atom_trial).  With
  *             negative weights p may round below zero by about one ulp of
- *             probs_base; eps of the cross-entropy should cover it.            */
+ *             probs_base; eps of the cross-entropy should cover it.
+ *   unitaries   NULL (Pauli settings), or [n_unitaries][2][2] complex128 device array
+ *             (row-major, re,im interleaved: 8 doubles each, 8-byte aligned) for
+ *             general local product measurements (the paper's descriptor-level
+ *             measurement actions): a code c >= 3 applies unitaries[c - 3] to its
+ *             qubit before the computational-basis readout.  The matrices are used
+ *             as given (unitarity is the caller's; p rows then sum to one).  Codes
+ *             >= 3 + n_unitaries act as the identity and raise the device flag.
+ *             Supported on QST_PATH_BUTTERFLY_F32 (and AUTO), one 2x2 per qubit and
+ *             setting instead of the Pauli butterflies.
+ *   n_unitaries 1..253 when unitaries is given, else ignored                   */
 typedef struct {
   int32_t n_qubits;
   int32_t rank;
@@ -131,6 +141,8 @@ typedef struct {
   const uint8_t* settings;
   const float* freqs;
   const void* probs_base;
+  const double* unitaries;
+  int32_t n_unitaries;
 } qst_instance;
 
 typedef struct qst_handle qst_handle;

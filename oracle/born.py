@@ -50,11 +50,12 @@ def density(atoms: np.ndarray, weights: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- forward
-def probs_dense(atoms, weights, settings) -> np.ndarray:
-    """Per-setting ``p[b,u] = B tr(E_{b,u} rho)`` from dense POVM effects (n <= 4)."""
+def probs_dense(atoms, weights, settings, table=None) -> np.ndarray:
+    """Per-setting ``p[b,u] = B tr(E_{b,u} rho)`` from dense POVM effects (n <= 4).
+    ``table``: the unitaries named by codes >= 3 (general local settings)."""
     settings = np.asarray(settings)
     B = settings.shape[0]
-    E = pauli.povm_elements(settings)
+    E = pauli.povm_elements(settings, table)
     rho = density(atoms, weights)
     D = rho.shape[0]
     p = np.zeros((B, D))
@@ -64,10 +65,10 @@ def probs_dense(atoms, weights, settings) -> np.ndarray:
     return p
 
 
-def atom_response_dense(atoms, settings) -> np.ndarray:
+def atom_response_dense(atoms, settings, table=None) -> np.ndarray:
     """Stacked atom-response matrix ``A[m, r] = <psi_r|E_m|psi_r>`` (``M = B*D`` rows)."""
     settings = np.asarray(settings)
-    E = pauli.povm_elements(settings)
+    E = pauli.povm_elements(settings, table)
     B, D = E.shape[0], E.shape[1]
     atoms = np.asarray(atoms, dtype=np.complex128)
     A = np.zeros((B * D, atoms.shape[0]))
@@ -78,32 +79,32 @@ def atom_response_dense(atoms, settings) -> np.ndarray:
     return A
 
 
-def probs_kron(atoms, weights, settings) -> np.ndarray:
+def probs_kron(atoms, weights, settings, table=None) -> np.ndarray:
     """``p[b,u] = sum_r alpha_r |(V_b psi_r)_u|^2`` with dense ``V_b`` (n <= 12)."""
     settings = np.asarray(settings)
     atoms = np.asarray(atoms, dtype=np.complex128)
     w = np.asarray(weights, dtype=np.float64)
     p = np.zeros((settings.shape[0], atoms.shape[1]))
     for b in range(settings.shape[0]):
-        V = pauli.setting_unitary(settings[b])
+        V = pauli.setting_unitary(settings[b], table)
         for r in range(atoms.shape[0]):
             p[b] += w[r] * np.abs(V @ atoms[r]) ** 2
     return p
 
 
-def rotate_axis(atoms, codes) -> np.ndarray:
+def rotate_axis(atoms, codes, table=None) -> np.ndarray:
     """``phi_r = V_b psi_r`` for every atom, per-axis contraction (any n)."""
-    return np.stack([pauli.apply_setting_axis(codes, a) for a in np.asarray(atoms)])
+    return np.stack([pauli.apply_setting_axis(codes, a, table=table) for a in np.asarray(atoms)])
 
 
-def probs_axis(atoms, weights, settings, rows=None) -> np.ndarray:
+def probs_axis(atoms, weights, settings, rows=None, table=None) -> np.ndarray:
     """``p[b,u]`` by per-axis contraction; ``rows`` restricts to a subset of settings."""
     settings = np.asarray(settings)
     w = np.asarray(weights, dtype=np.float64)
     rows = range(settings.shape[0]) if rows is None else rows
     out = []
     for b in rows:
-        phi = rotate_axis(atoms, settings[b])
+        phi = rotate_axis(atoms, settings[b], table)
         out.append(np.einsum("r,ru->u", w, np.abs(phi) ** 2))
     return np.asarray(out)
 
@@ -180,14 +181,14 @@ def likelihood_ratio(p, f, B: int, eps: float) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- gradients
-def gradients_dense(atoms, weights, settings, g):
+def gradients_dense(atoms, weights, settings, g, table=None):
     """Gradients from dense POVM effects (n <= 4), given ``g = dL/dp`` (per setting).
 
     With ``dL/dpi_m = B g_m``:  ``dL/dpsi_r^* = alpha_r sum_m (B g_m) E_m psi_r`` and
     ``dL/dalpha_r = sum_m (B g_m) <psi_r|E_m|psi_r>``.
     """
     settings = np.asarray(settings)
-    E = pauli.povm_elements(settings)
+    E = pauli.povm_elements(settings, table)
     B, D = E.shape[0], E.shape[1]
     atoms = np.asarray(atoms, dtype=np.complex128)
     w = np.asarray(weights, dtype=np.float64)
@@ -202,11 +203,11 @@ def gradients_dense(atoms, weights, settings, g):
     return ga, gw
 
 
-def gradient_matrix_dense(settings, g) -> np.ndarray:
+def gradient_matrix_dense(settings, g, table=None) -> np.ndarray:
     """``G = -grad_rho L = -sum_m (dL/dpi_m) E_m``; for CE this is ``sum_m c_m E_m``
     (eqs. density-gradient, negative-gradient-matrix)."""
     settings = np.asarray(settings)
-    E = pauli.povm_elements(settings)
+    E = pauli.povm_elements(settings, table)
     B, D = E.shape[0], E.shape[1]
     G = np.zeros((D, D), dtype=np.complex128)
     for b in range(B):
@@ -215,7 +216,7 @@ def gradient_matrix_dense(settings, g) -> np.ndarray:
     return G
 
 
-def gradients_kron(atoms, weights, settings, g):
+def gradients_kron(atoms, weights, settings, g, table=None):
     """Same gradients with dense per-setting ``V_b`` (n <= 12)."""
     settings = np.asarray(settings)
     atoms = np.asarray(atoms, dtype=np.complex128)
@@ -225,7 +226,7 @@ def gradients_kron(atoms, weights, settings, g):
     ga = np.zeros((R, D), dtype=np.complex128)
     gw = np.zeros(R)
     for b in range(settings.shape[0]):
-        V = pauli.setting_unitary(settings[b])
+        V = pauli.setting_unitary(settings[b], table)
         for r in range(R):
             phi = V @ atoms[r]
             ga[r] += w[r] * (V.conj().T @ (g[b] * phi))
@@ -233,7 +234,7 @@ def gradients_kron(atoms, weights, settings, g):
     return ga, gw
 
 
-def gradients_axis(atoms, weights, settings, g, rows=None):
+def gradients_axis(atoms, weights, settings, g, rows=None, table=None):
     """Same gradients by per-axis contraction; ``rows`` selects a subset of settings
     (``g`` then has one row per selected setting).  The adjoint is a sum over
     settings, so a subset gives the exact partial sum."""
@@ -247,18 +248,19 @@ def gradients_axis(atoms, weights, settings, g, rows=None):
     gw = np.zeros(R)
     for i, b in enumerate(rows):
         for r in range(R):
-            phi = pauli.apply_setting_axis(settings[b], atoms[r])
-            ga[r] += w[r] * pauli.apply_setting_axis(settings[b], g[i] * phi, adjoint=True)
+            phi = pauli.apply_setting_axis(settings[b], atoms[r], table=table)
+            ga[r] += w[r] * pauli.apply_setting_axis(settings[b], g[i] * phi, adjoint=True, table=table)
             gw[r] += np.sum(g[i] * np.abs(phi) ** 2)
     return ga, gw
 
 
-def apply_gradient_matrix_axis(settings, g, v) -> np.ndarray:
+def apply_gradient_matrix_axis(settings, g, v, table=None) -> np.ndarray:
     """Matrix-free ``G v = -sum_b V_b^dagger (g_b * V_b v)`` (eq. negative-gradient-product)."""
     settings = np.asarray(settings)
     out = np.zeros(np.asarray(v).shape[0], dtype=np.complex128)
     for b in range(settings.shape[0]):
-        out -= pauli.apply_setting_axis(settings[b], g[b] * pauli.apply_setting_axis(settings[b], v), adjoint=True)
+        out -= pauli.apply_setting_axis(settings[b], g[b] * pauli.apply_setting_axis(settings[b], v, table=table),
+                                        adjoint=True, table=table)
     return out
 
 
@@ -275,17 +277,19 @@ def tangent_project(atoms, atom_grad) -> np.ndarray:
 
 # ---------------------------------------------------------------- composite
 def forward_backward(atoms, weights, settings, f, kind: int, eps: float, tier: str = "axis",
-                     grad_p=None):
+                     grad_p=None, table=None):
     """Loss, per-setting probabilities and both gradients, by the chosen tier.
 
-    If ``grad_p`` is given it is used as ``g`` (generic mode, loss = None)."""
+    If ``grad_p`` is given it is used as ``g`` (generic mode, loss = None).  ``table``
+    holds the unitaries of codes >= 3 (general local settings)."""
     settings = np.asarray(settings)
     B = settings.shape[0]
-    probs = {"dense": probs_dense, "kron": probs_kron, "axis": probs_axis}[tier](atoms, weights, settings)
+    probs = {"dense": probs_dense, "kron": probs_kron, "axis": probs_axis}[tier](atoms, weights, settings,
+                                                                                  table=table)
     if grad_p is None:
         L, g = loss_and_sensitivity(probs, f, B, kind, eps)
     else:
         L, g = None, np.asarray(grad_p, dtype=np.float64)
     grads = {"dense": gradients_dense, "kron": gradients_kron, "axis": gradients_axis}[tier]
-    ga, gw = grads(atoms, weights, settings, g)
+    ga, gw = grads(atoms, weights, settings, g, table=table)
     return L, probs, ga, gw

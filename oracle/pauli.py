@@ -12,6 +12,11 @@ the three matrices; the readings used here (and recorded as such) are
 so outcome bit 0 is the +1 eigenvector.  Qubit ``j`` (0-based; qubit 0 is the
 leftmost Kronecker factor) is bit ``N-1-j`` of both the amplitude index and
 the outcome index -- i.e. axis ``j`` of a C-ordered ``(2,)*N`` reshape.
+
+General local product measurements (the measurement-action section allows any
+local or tensor-product POVM given by its descriptors): a code ``c >= 3`` names
+the caller's unitary ``table[c - 3]`` (a 2x2 complex matrix applied before the
+computational-basis readout), so a setting is still one code per qubit.
 """
 from __future__ import annotations
 
@@ -34,20 +39,23 @@ SIGMA = {
 }
 
 
-def single(code: int) -> np.ndarray:
-    """2x2 rotation for one Pauli code (X=0, Y=1, Z=2)."""
-    return V_SINGLE[int(code)]
+def single(code: int, table=None) -> np.ndarray:
+    """2x2 rotation for one code: X=0, Y=1, Z=2, or ``table[code - 3]`` for ``code >= 3``."""
+    code = int(code)
+    if code <= Z:
+        return V_SINGLE[code]
+    return np.asarray(table, dtype=np.complex128)[code - 3]
 
 
-def setting_unitary(codes) -> np.ndarray:
+def setting_unitary(codes, table=None) -> np.ndarray:
     """Dense ``V_b = kron(V_{s_0}, ..., V_{s_{N-1}})`` (D x D); qubit 0 is the leftmost factor."""
     V = np.ones((1, 1), dtype=np.complex128)
     for c in codes:
-        V = np.kron(V, single(c))
+        V = np.kron(V, single(c, table))
     return V
 
 
-def apply_setting_axis(codes, vec: np.ndarray, adjoint: bool = False) -> np.ndarray:
+def apply_setting_axis(codes, vec: np.ndarray, adjoint: bool = False, table=None) -> np.ndarray:
     """``V_b vec`` (or ``V_b^dagger vec``) by contracting each 2x2 along its own axis.
 
     ``vec`` has length ``2^N``; it is viewed as a ``(2,)*N`` tensor whose axis ``j``
@@ -58,14 +66,14 @@ def apply_setting_axis(codes, vec: np.ndarray, adjoint: bool = False) -> np.ndar
     for j, c in enumerate(codes):
         if int(c) == Z:
             continue
-        U = single(c)
+        U = single(c, table)
         if adjoint:
             U = U.conj().T
         t = np.moveaxis(np.tensordot(U, t, axes=([1], [j])), 0, j)
     return t.reshape(-1)
 
 
-def povm_elements(settings) -> np.ndarray:
+def povm_elements(settings, table=None) -> np.ndarray:
     """All effects ``E_{b,u} = (1/B) V_b^dagger |u><u| V_b`` as a ``[B][D][D][D]`` array.
 
     Only for tiny ``N`` (dense tier).
@@ -75,7 +83,7 @@ def povm_elements(settings) -> np.ndarray:
     D = 1 << N
     E = np.zeros((B, D, D, D), dtype=np.complex128)
     for b in range(B):
-        V = setting_unitary(settings[b])
+        V = setting_unitary(settings[b], table)
         for u in range(D):
             w = V[u, :].conj()  # V_b^dagger e_u
             E[b, u] = np.outer(w, w.conj()) / B

@@ -41,6 +41,8 @@ class QstInstance(ctypes.Structure):
         ("settings", ctypes.c_void_p),
         ("freqs", ctypes.c_void_p),
         ("probs_base", ctypes.c_void_p),
+        ("unitaries", ctypes.c_void_p),
+        ("n_unitaries", ctypes.c_int32),
     ]
 
 

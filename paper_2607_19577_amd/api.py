@@ -94,7 +94,8 @@ class Handle:
 class Instance:
     """One tomography instance: atoms [R][D] complex, weights [R] float64,
     settings [B][N] uint8 (X=0, Y=1, Z=2), freqs [B][D] float32 (optional),
-    probs_base [B][D] of the path's real type (optional: p = probs_base + the atoms' part)."""
+    probs_base [B][D] of the path's real type (optional: p = probs_base + the atoms' part),
+    unitaries [K][2][2] complex128 (optional: settings codes c >= 3 apply unitaries[c - 3])."""
 
     atoms: torch.Tensor
     weights: torch.Tensor
@@ -102,6 +103,7 @@ class Instance:
     freqs: Optional[torch.Tensor] = None
     settings_per_batch: int = 0  # 0: library default
     probs_base: Optional[torch.Tensor] = None
+    unitaries: Optional[torch.Tensor] = None
 
     @property
     def shape(self):
@@ -127,10 +129,15 @@ class Instance:
         pb = self.probs_base
         if pb is not None and (pb.dtype != _real_of(path) or not pb.is_contiguous() or tuple(pb.shape) != (B, 1 << N)):
             raise ValueError("probs_base must be contiguous [B][2^N] of the path's real type")
+        u = self.unitaries
+        if u is not None and (u.dtype != torch.complex128 or not u.is_contiguous() or u.dim() != 3
+                              or tuple(u.shape[1:]) != (2, 2)):
+            raise ValueError("unitaries must be contiguous [K][2][2] complex128")
         return QstInstance(N, R, B, int(self.settings_per_batch), self.atoms.data_ptr(), self.weights.data_ptr(),
                            self.settings.data_ptr(),
                            None if self.freqs is None else self.freqs.data_ptr(),
-                           None if pb is None else pb.data_ptr())
+                           None if pb is None else pb.data_ptr(),
+                           None if u is None else u.data_ptr(), 0 if u is None else int(u.shape[0]))
 
 
 def _structs(insts: Sequence[Instance], path: int):

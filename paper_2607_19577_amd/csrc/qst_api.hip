@@ -203,7 +203,7 @@ void set_grid(qst_handle* h, Geometry& g, int S) {
   const long long chunks = (long long)S << g.n_hi;
   int per_cu = 1;
   if (h->device >= 0) {
-    const auto key = std::make_tuple(g.n_lo, (g.n_hi > 0 ? 1 : 0) | (g.h16 ? 2 : 0), g.R, g.elem);
+    const auto key = std::make_tuple(g.n_lo, (g.n_hi > 0 ? 1 : 0) | (g.h16 ? 2 : 0) | (g.gen ? 4 : 0), g.R, g.elem);
     auto it = h->occupancy.find(key);
     if (it == h->occupancy.end()) it = h->occupancy.emplace(key, qst::lo_blocks_per_cu(g)).first;
     per_cu = it->second;
@@ -235,7 +235,7 @@ int default_S(const Geometry& g) {
 }
 
 struct WsLayout {
-  size_t pc, X, W, part, lvl1, sums, tan, gneg, split, total;
+  size_t pc, um, X, W, part, lvl1, sums, tan, gneg, split, total;
 };
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -252,6 +252,8 @@ WsLayout layout_ws(const Geometry& g, int S, qst_path path, bool with_gneg, size
   const size_t vec = (size_t)S * g.R * g.D * 2 * (g.h16 ? 2 : g.elem);
   L.pc = o;
   o = al256(o + (size_t)g.B * 8);
+  L.um = o;
+  if (g.gen) o = al256(o + (size_t)g.B * g.n * 8 * sizeof(float));
   L.X = o;
   if (g.n_hi > 0 || pass_path(path)) o = al256(o + vec);
   L.W = o;
@@ -279,7 +281,8 @@ qst_status check_flag(qst_handle* h) {
   if (*h->hflag) {
     *h->hflag = 0;
     qst::launch_fill(h->dflag, sizeof(int), h->stream);
-    return set_err(h, QST_ERR_NUMERIC, "a setting held a Pauli code > 2 (treated as Z)");
+    return set_err(h, QST_ERR_NUMERIC,
+                   "a setting held a code outside the Pauli codes and the unitary table (treated as the identity)");
   }
   return QST_OK;
 }
@@ -305,6 +308,12 @@ qst_status validate_instance(qst_handle* h, const qst_instance& in, qst_path pat
   if (!aligned(in.atoms, ea) || !aligned(in.weights, 8) || (in.freqs && !aligned(in.freqs, 4)) ||
       (in.probs_base && !aligned(in.probs_base, (size_t)elem_of(path))))
     return set_err(h, QST_ERR_ALIGN, "atoms/weights/freqs/probs_base not aligned to their element size");
+  if (in.unitaries) {
+    if (path != QST_PATH_BUTTERFLY_F32)
+      return set_err(h, QST_ERR_UNSUPPORTED, "general local settings run on QST_PATH_BUTTERFLY_F32");
+    if (in.n_unitaries < 1 || in.n_unitaries > 253) return set_err(h, QST_ERR_SHAPE, "n_unitaries must be in 1..253");
+    if (!aligned(in.unitaries, 8)) return set_err(h, QST_ERR_ALIGN, "unitaries not 8-byte aligned");
+  }
   return QST_OK;
 }
 
@@ -341,6 +350,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   Geometry g;
   qst_status st = make_geometry(h, in.n_qubits, in.rank, in.n_settings, path, g);
   if (st != QST_OK) return st;
+  g.gen = in.unitaries != nullptr;
   const int S = batch_size(h, g, in, path, rs.S_override);
   set_grid(h, g, S);
   const WsLayout L = layout_ws(g, S, path, false, ws_base);
@@ -356,14 +366,19 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   double* sums = reinterpret_cast<double*>(ws + L.sums);
   hipStream_t s = h->stream;
 
+  float* um = g.gen ? reinterpret_cast<float*>(ws + L.um) : nullptr;
   prof_begin(h, PK_DECODE);
-  QST_HIP(qst::launch_decode(in.settings, g.B, g.n, pc, h->dflag, s));
+  if (g.gen)
+    QST_HIP(qst::launch_decode_general(in.settings, g.B, g.n, in.unitaries, in.n_unitaries, um, pc, h->dflag, s));
+  else
+    QST_HIP(qst::launch_decode(in.settings, g.B, g.n, pc, h->dflag, s));
   prof_end(h);
   const bool want_loss = rs.grad_p == nullptr && rs.loss_kind != QST_LOSS_NONE;
   const long long nslots = nslots_of(g, path);
 
   qst::LoArgs la{};
   la.pc = pc;
+  la.um = um;
   la.alpha = in.weights;
   la.freqs = in.freqs;
   la.grad_p = rs.grad_p;
@@ -418,6 +433,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
       ha.src = in.atoms;
       ha.dst = X;
       ha.pc = pc;
+      ha.um = um;
       ha.D = g.D;
       ha.R = g.R;
       ha.n = g.n;
@@ -457,6 +473,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
         hc.src = W;
         hc.dst = rs.atom_grad;
         hc.pc = pc;
+        hc.um = um;
         hc.D = g.D;
         hc.R = g.R;
         hc.n = g.n;
@@ -666,7 +683,7 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
     Geometry g;
     qst_status st = make_geometry(h, r.in->n_qubits, r.in->rank, r.in->n_settings, r.path, g);
     if (st != QST_OK) return st;
-    if (specs.size() > 1 && batchable(g, r.path) && r.in->settings_per_batch <= 0)
+    if (specs.size() > 1 && batchable(g, r.path) && r.in->settings_per_batch <= 0 && !r.in->unitaries)
       groups[r.in->n_qubits].push_back(&r);
     else
       single.push_back(&r);
@@ -695,6 +712,7 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
       Geometry g;
       qst_status st = make_geometry(h, r->in->n_qubits, r->in->rank, r->in->n_settings, r->path, g);
       if (st != QST_OK) return st;
+      g.gen = r->in->unitaries != nullptr;
       const int S = batch_size(h, g, *r->in, r->path, 0);
       set_grid(h, g, S);
       *need = std::max(*need, layout_ws(g, S, r->path, false).total);
@@ -909,6 +927,7 @@ qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_pat
     Geometry g;
     st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, path, g);
     if (st != QST_OK) return st;
+    g.gen = inst[i].unitaries != nullptr;
     int S = default_S(g);
     if (h->device < 0) continue;
     if (autotune && !pass_path(path) && g.n_hi > 0) {
@@ -1110,6 +1129,7 @@ qst_status qst_atom_trial(qst_handle* h, const qst_instance* inst, int r, const 
   Geometry g;
   st = make_geometry(h, inst->n_qubits, 2, inst->n_settings, path, g);
   if (st != QST_OK) return st;
+  g.gen = inst->unitaries != nullptr;
   st = device_gate(h);
   if (st != QST_OK) return st;
 
@@ -1199,6 +1219,7 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
   if (st != QST_OK) return st;
   st = make_geometry(h, n, 1, B, path, g1);
   if (st != QST_OK) return st;
+  gR.gen = g1.gen = inst->unitaries != nullptr;
   const int k_max = (int)std::min<long long>(n_lanczos, D);
   hipStream_t s = h->stream;
 

@@ -127,6 +127,46 @@ __device__ __forceinline__ void xform_xz(T (&x)[1 << LOGV], T (&y)[1 << LOGV], u
   xform_xz_bit<0, LOGV, ACTIVE>(x, y, codes);
 }
 
+// General local settings: register bit K applies the 2x2 complex matrix at
+// um + 8 (qidx0 + K) (a00, a01, a10, a11 as re, im pairs; uniform across the
+// work-group), or its conjugate transpose (ADJ):  a' = m00 a + m01 b, b' = m10 a + m11 b.
+// Sixteen multiply-adds per pair; no phase split and no skipped bits (the decode
+// writes the identity for Z).
+template <int K, int LOGV, bool ADJ, uint32_t ACTIVE, typename T>
+__device__ __forceinline__ void xform_gen_bit(T (&x)[1 << LOGV], T (&y)[1 << LOGV], const float* um, int qidx0) {
+  if constexpr (K < LOGV) {
+    if constexpr ((ACTIVE >> K) & 1u) {
+      const float* m = um + 8 * (qidx0 + K);
+      T m00r = m[0], m00i = m[1], m01r = m[2], m01i = m[3], m10r = m[4], m10i = m[5], m11r = m[6], m11i = m[7];
+      if constexpr (ADJ) {  // conjugate transpose
+        const T t0 = m01r, t1 = m01i;
+        m01r = m10r;
+        m01i = -m10i;
+        m10r = t0;
+        m10i = -t1;
+        m00i = -m00i;
+        m11i = -m11i;
+      }
+#pragma unroll
+      for (int i = 0; i < (1 << LOGV); ++i) {
+        if (i & (1 << K)) continue;
+        const int j = i | (1 << K);
+        const T ax = x[i], ay = y[i], bx = x[j], by = y[j];
+        x[i] = fma(m00r, ax, fma(-m00i, ay, fma(m01r, bx, -m01i * by)));
+        y[i] = fma(m00r, ay, fma(m00i, ax, fma(m01r, by, m01i * bx)));
+        x[j] = fma(m10r, ax, fma(-m10i, ay, fma(m11r, bx, -m11i * by)));
+        y[j] = fma(m10r, ay, fma(m10i, ax, fma(m11r, by, m11i * bx)));
+      }
+    }
+    xform_gen_bit<K + 1, LOGV, ADJ, ACTIVE>(x, y, um, qidx0);
+  }
+}
+
+template <int LOGV, bool ADJ, uint32_t ACTIVE, typename T>
+__device__ __forceinline__ void xform_gen(T (&x)[1 << LOGV], T (&y)[1 << LOGV], const float* um, int qidx0) {
+  xform_gen_bit<0, LOGV, ADJ, ACTIVE>(x, y, um, qidx0);
+}
+
 // Orders the LDS accesses of a wavefront around an exchange between its lanes.
 // A wavefront's LDS operations execute in issue order; the fences keep the
 // compiler from reordering accesses across this point and emit no instruction.

@@ -6,8 +6,11 @@ namespace qst {
 
 // Supported (tile bits, high bits) pairs of the FP32 path: n in 11..20 with the
 // low-stage sizes chosen by the host (n_lo >= 10).
+hipError_t launch_stage_hi_gen(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st);
+
 hipError_t launch_stage_hi(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st) {
   if (g.elem != 4 || a.nsplit < 1 || a.nsplit > a.S) return hipErrorInvalidValue;
+  if (g.gen) return g.h16 ? hipErrorInvalidValue : launch_stage_hi_gen(g, a, adjoint, st);
 #define QST_HI(TBv, NHv)                                                       \
   if (g.t == TBv && g.n_hi == NHv)                                             \
     return g.h16 ? launch_hi_n<TBv, NHv, true>(g, a, adjoint, st)              \

@@ -25,6 +25,7 @@ struct Geometry {
   int elem;      // bytes per real (4 or 8)
   int split_adj; // work-groups per adjoint tile at batch size S (partial-sum slices in the workspace)
   bool h16;      // the setting-batch intermediates X and W are stored in BF16
+  bool gen;      // general local settings: one 2x2 matrix per (setting, qubit) from the decode
 };
 
 struct LoArgs {
@@ -37,6 +38,7 @@ struct LoArgs {
   const void* grad_p;         // [B][D] or null (generic sensitivity)
   void* probs;                // [B][D] or null
   const void* pbase;          // [B][D] or null: base probabilities added to p
+  const float* um;            // general settings: [B][n][8] matrices by index bit (else null)
   void* gneg;                 // [B][D] or null: receives -dL/dp
   double* part;               // [(R+1)][nslots]: row 0 loss, rows 1..R weight gradient
   long long nslots;
@@ -65,6 +67,7 @@ struct HiArgs {
   const void* src;  // forward: atoms [R][D];   adjoint: W [S][R][D]
   void* dst;        // forward: X [S][R][D];    adjoint: atom gradient [R][D]
   const uint64_t* pc;
+  const float* um;  // general settings: [B][n][8] matrices by index bit (else null)
   void* part;       // adjoint with nsplit > 1: per-split sums [nsplit][R][D]
   long long D;
   int R, n, n_lo, n_hi, t, c, b0, S, first;
@@ -125,6 +128,11 @@ hipError_t launch_stage_lo(const Geometry& g, const LoBatch& m, bool adjoint, hi
 hipError_t launch_stage_hi(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_sum_settings(const Geometry& g, const void* W, int S, void* grad, int first, hipStream_t st);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
+// General local settings: per (setting, qubit) the normalised 2x2 matrix (Pauli codes
+// 0..2 or unitaries[code - 3]) as 8 floats at um[(b * N + index bit) * 8]; pc gets code 0
+// for every qubit.  Codes >= 3 + K raise the flag and apply the identity.
+hipError_t launch_decode_general(const uint8_t* settings, int B, int N, const double* unitaries, int K, float* um,
+                                 uint64_t* pc, int* flag, hipStream_t st);
 // part [rows][nslots] -> out[rows] (two-level, fixed order).  out_stride: spacing of out entries.
 hipError_t launch_rowsum(const double* part, int rows, long long nslots, double* lvl1, int g1, double* out,
                          hipStream_t st);

@@ -37,6 +37,46 @@ hipError_t launch_decode(const uint8_t* settings, int B, int N, uint64_t* pc, in
   return hipGetLastError();
 }
 
+// General local settings: thread (b, j) writes the normalised 2x2 matrix of qubit j
+// of setting b at um[(b N + N-1-j) 8 ..] (FP32; a00, a01, a10, a11 as re, im pairs):
+// the Pauli rotations for codes 0..2 (V_Z = I), unitaries[code - 3] (complex128)
+// beyond.  pc gets code 0 everywhere (every bit is applied).
+__global__ void k_decode_general(const uint8_t* __restrict__ settings, int B, int N,
+                                 const double* __restrict__ unitaries, int K, float* __restrict__ um,
+                                 uint64_t* __restrict__ pc, int* __restrict__ flag) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= (long long)B * N) return;
+  const int b = (int)(t / N);
+  const int j = (int)(t - (long long)b * N);
+  const uint32_t c = settings[t];
+  constexpr float r2 = 0.70710678118654752440f;
+  float m[8] = {1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
+  if (c == 0u) {
+    const float v[8] = {r2, 0.f, r2, 0.f, r2, 0.f, -r2, 0.f};
+    for (int k = 0; k < 8; ++k) m[k] = v[k];
+  } else if (c == 1u) {
+    const float v[8] = {r2, 0.f, 0.f, -r2, r2, 0.f, 0.f, r2};
+    for (int k = 0; k < 8; ++k) m[k] = v[k];
+  } else if (c >= 3u) {
+    if ((int)(c - 3u) < K) {
+      for (int k = 0; k < 8; ++k) m[k] = (float)unitaries[(size_t)(c - 3u) * 8 + k];
+    } else {
+      atomicOr(flag, 1);
+    }
+  }
+  float* dst = um + ((size_t)b * N + (N - 1 - j)) * 8;
+  for (int k = 0; k < 8; ++k) dst[k] = m[k];
+  if (j == 0) pc[b] = 0ull;
+}
+
+hipError_t launch_decode_general(const uint8_t* settings, int B, int N, const double* unitaries, int K, float* um,
+                                 uint64_t* pc, int* flag, hipStream_t st) {
+  const long long n = (long long)B * N;
+  const int bs = 256;
+  k_decode_general<<<(unsigned)((n + bs - 1) / bs), bs, 0, st>>>(settings, B, N, unitaries, K, um, pc, flag);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ fill
 __global__ void k_fill(uint32_t* p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
@@ -72,13 +112,16 @@ size_t lo_lds_bytes(const Geometry& g) {
 hipError_t launch_stage_lo_f32(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
 hipError_t launch_stage_lo_h16(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
 hipError_t launch_stage_lo_f64(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
+hipError_t launch_stage_lo_gen(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
 int lo_occupancy_f32(const Geometry& g);
+int lo_occupancy_gen(const Geometry& g);
 int lo_occupancy_h16(const Geometry& g);
 int lo_occupancy_f64(const Geometry& g);
 
 hipError_t launch_stage_lo(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
   if (m.count < 1 || m.count > kBatchMax || m.rmax != g.R) return hipErrorInvalidValue;
-  if (g.elem != 4) return launch_stage_lo_f64(g, m, adjoint, st);
+  if (g.elem != 4) return g.gen ? hipErrorInvalidValue : launch_stage_lo_f64(g, m, adjoint, st);
+  if (g.gen) return g.h16 ? hipErrorInvalidValue : launch_stage_lo_gen(g, m, adjoint, st);
   return g.h16 ? launch_stage_lo_h16(g, m, adjoint, st) : launch_stage_lo_f32(g, m, adjoint, st);
 }
 
@@ -86,6 +129,7 @@ hipError_t launch_stage_lo(const Geometry& g, const LoBatch& m, bool adjoint, hi
 // times the number of compute units).
 int lo_blocks_per_cu(const Geometry& g) {
   if (g.elem != 4) return lo_occupancy_f64(g);
+  if (g.gen) return lo_occupancy_gen(g);
   return g.h16 ? lo_occupancy_h16(g) : lo_occupancy_f32(g);
 }
 

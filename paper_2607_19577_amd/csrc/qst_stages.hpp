@@ -89,23 +89,33 @@ constexpr uint32_t chain_mask() {
   return m;
 }
 
-// Butterflies of every layout of the chain, first to last.
-template <int K, typename CH, bool WL, int LOGV, typename T>
-__device__ __forceinline__ void fwd_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc) {
+// Butterflies of every layout of the chain, first to last.  GEN: the general 2x2
+// matrices of the setting (um, by index bit) instead of the Pauli butterflies.
+template <int K, typename CH, bool WL, bool GEN, int LOGV, typename T>
+__device__ __forceinline__ void fwd_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc,
+                                          const float* um) {
   if constexpr (K < CH::count()) {
     if constexpr (K > 0) lo_transpose<WL, LOGV, CH::lo(K - 1), CH::lo(K)>(x, y, re, im, tau);
-    xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
-    fwd_chain<K + 1, CH, WL, LOGV>(x, y, re, im, tau, pc);
+    if constexpr (GEN)
+      xform_gen<LOGV, false, chain_mask<CH, K>()>(x, y, um, CH::lo(K));
+    else
+      xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
+    fwd_chain<K + 1, CH, WL, GEN, LOGV>(x, y, re, im, tau, pc, um);
   }
 }
 
-// The same butterflies from the last layout back to layout 0 (each is its own adjoint).
-template <int K, typename CH, bool WL, int LOGV, typename T>
-__device__ __forceinline__ void adj_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc) {
-  xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
+// The adjoint butterflies from the last layout back to layout 0 (the Pauli ones are
+// their own adjoints; the general ones take the conjugate transpose).
+template <int K, typename CH, bool WL, bool GEN, int LOGV, typename T>
+__device__ __forceinline__ void adj_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc,
+                                          const float* um) {
+  if constexpr (GEN)
+    xform_gen<LOGV, true, chain_mask<CH, K>()>(x, y, um, CH::lo(K));
+  else
+    xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
   if constexpr (K > 0) {
     lo_transpose<WL, LOGV, CH::lo(K), CH::lo(K - 1)>(x, y, re, im, tau);
-    adj_chain<K - 1, CH, WL, LOGV>(x, y, re, im, tau, pc);
+    adj_chain<K - 1, CH, WL, GEN, LOGV>(x, y, re, im, tau, pc, um);
   }
 }
 
@@ -139,9 +149,11 @@ __device__ __forceinline__ void apply_phase(T (&x)[1 << LOGV], T (&y)[1 << LOGV]
 // prefetches the next chunk's amplitudes and data row while it works on the
 // current one.  Its loss and weight-gradient partials go to one slot per
 // (batch, work-group), so the final sums do not depend on timing.
-// H16: the setting-batch intermediates X (input, when the state has high bits) and W
-// (output) are stored in BF16; arithmetic stays in T.
-template <typename T, int N_LO, bool ADJ, bool PHASE, bool H16>
+// PHASE: the state is one chunk (n = n_lo): the input is the atoms and this stage
+// applies the Y phases.  H16: the setting-batch intermediates X (input, when the state
+// has high bits) and W (output) are stored in BF16; arithmetic stays in T.  GEN:
+// general local settings (normalised 2x2 matrices per qubit, no phases, scale 1).
+template <typename T, int N_LO, bool ADJ, bool PHASE, bool H16, bool GEN = false>
 __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
   using C2 = cx<T>;
   constexpr int LOGV = N_LO < 5 ? N_LO : 5;
@@ -273,7 +285,8 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
     const bool active = atom < a.R;
     const T al = active ? (T)a.alpha[atom] : T(0);
     const uint64_t pc = uniform_u64(a.pc[b]);
-    const T s2 = (T)ldexp(1.0, -nonz_count(pc, a.n));
+    const T s2 = GEN ? T(1) : (T)ldexp(1.0, -nonz_count(pc, a.n));
+    const float* um = GEN ? a.um + (size_t)b * a.n * 8 : nullptr;
     const double Bd = (double)a.B;
     const float inv_b = (float)(1.0 / Bd);
     const float eps_f = (float)a.eps;
@@ -283,11 +296,11 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
     for (int j = 0; j < NPF; ++j) fv[j] = bf[j];
 
     uint32_t ym = 0;
-    if constexpr (PHASE) {
+    if constexpr (PHASE && !GEN) {
       ym = ymask_of(pc, a.n);
       apply_phase<false, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
     }
-    fwd_chain<0, CH, WL, LOGV>(x, y, re, im, tau, pc);
+    fwd_chain<0, CH, WL, GEN, LOGV>(x, y, re, im, tau, pc, um);
     // Final layout is lo = 0: alpha_r |phi_r|^2 into LDS, reduced over atoms per outcome.
     T* qrow = qb + (size_t)atom * UPAD + pad_base<LOGV, 0>(tau);
 #pragma unroll
@@ -377,8 +390,8 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
       }
       h_acc += (double)hl;
       if constexpr (!WL) __syncthreads();  // every thread has read g before the planes are reused
-      adj_chain<NL - 1, CH, WL, LOGV>(x, y, re, im, tau, pc);
-      if constexpr (PHASE) apply_phase<true, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
+      adj_chain<NL - 1, CH, WL, GEN, LOGV>(x, y, re, im, tau, pc, um);
+      if constexpr (PHASE && !GEN) apply_phase<true, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
       unsigned char* dbase = reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + ((long long)h << N_LO)) * CBO;
       const rsrc_t rd = make_rsrc(dbase, extent(a, CBO));
       const uint32_t vo0 = voff(a, CBO);
@@ -408,33 +421,33 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
   }
 }
 
-template <typename T, int N_LO, bool PHASE, bool H16>
+template <typename T, int N_LO, bool PHASE, bool H16, bool GEN = false>
 hipError_t launch_lo_n(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
   constexpr int LOGV = N_LO < 5 ? N_LO : 5;
   const int nthr = m.rmax << (N_LO - LOGV);
   const size_t lds = lo_lds_bytes(g);
   const unsigned grid = (unsigned)g.grid_lo;
   if (adjoint) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16, GEN>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_lo<T, N_LO, true, PHASE, H16><<<grid, nthr, lds, st>>>(m);
+    k_stage_lo<T, N_LO, true, PHASE, H16, GEN><<<grid, nthr, lds, st>>>(m);
   } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, false, PHASE, H16>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, false, PHASE, H16, GEN>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_lo<T, N_LO, false, PHASE, H16><<<grid, nthr, lds, st>>>(m);
+    k_stage_lo<T, N_LO, false, PHASE, H16, GEN><<<grid, nthr, lds, st>>>(m);
   }
   return hipGetLastError();
 }
 
-template <typename T, int N_LO, bool PHASE, bool H16>
+template <typename T, int N_LO, bool PHASE, bool H16, bool GEN = false>
 int lo_occupancy_n(const Geometry& g) {
   constexpr int LOGV = N_LO < 5 ? N_LO : 5;
   const int nthr = g.R << (N_LO - LOGV);
   const size_t lds = lo_lds_bytes(g);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16>),
+  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16, GEN>),
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_stage_lo<T, N_LO, true, PHASE, H16>, nthr, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_stage_lo<T, N_LO, true, PHASE, H16, GEN>, nthr, lds) !=
       hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
@@ -456,8 +469,9 @@ constexpr uint32_t rows_mask(int lo, int c, int top) {
   return m;
 }
 
-// H16: X (forward output) and W (adjoint input) are stored in BF16.
-template <int TB, int N_HI, bool ADJ, bool H16>
+// H16: X (forward output) and W (adjoint input) are stored in BF16.  GEN: general
+// local settings (the setting's 2x2 matrices of the high bits, no phases).
+template <int TB, int N_HI, bool ADJ, bool H16, bool GEN = false>
 __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   using T = float;
   using C2 = float2;
@@ -507,18 +521,27 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
     }
     for (int s = s_lo; s < s_hi; ++s) {
       const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
-      const uint32_t ym = ymask_of(pc, a.n);
       T x[V], y[V];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         x[i] = kx[i];
         y[i] = ky[i];
       }
-      apply_phase<false, LOGV>(x, y, cbase | t0, ym, off0);
-      xform_xz<LOGV, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
-      if constexpr (TWO) {
-        lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
-        xform_xz<LOGV, M1>(x, y, layout_codes<LOGV>(pc, LO1, LO1, LO0, C, n_lo));
+      if constexpr (GEN) {
+        // register bit k of layout lo is index bit n_lo + lo + k - C
+        const float* um = a.um + (size_t)(a.b0 + s) * a.n * 8;
+        xform_gen<LOGV, false, M0>(x, y, um, n_lo + LO0 - C);
+        if constexpr (TWO) {
+          lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
+          xform_gen<LOGV, false, M1>(x, y, um, n_lo + LO1 - C);
+        }
+      } else {
+        apply_phase<false, LOGV>(x, y, cbase | t0, ymask_of(pc, a.n), off0);
+        xform_xz<LOGV, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
+        if constexpr (TWO) {
+          lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
+          xform_xz<LOGV, M1>(x, y, layout_codes<LOGV>(pc, LO1, LO1, LO0, C, n_lo));
+        }
       }
       const rsrc_t rx =
           make_rsrc(reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + origin) * CBH, vbytes_h);
@@ -541,14 +564,23 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
       }
     };
     auto body = [&](int s, T (&x)[V], T (&y)[V]) __attribute__((always_inline)) {
-      const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
-      const uint32_t ym = ymask_of(pc, a.n);
-      xform_xz<LOGV, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
-      if constexpr (TWO) {
-        lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
-        xform_xz<LOGV, M1>(x, y, layout_codes<LOGV>(pc, LO1, LO1, LO0, C, n_lo));
+      if constexpr (GEN) {
+        const float* um = a.um + (size_t)(a.b0 + s) * a.n * 8;
+        xform_gen<LOGV, true, M0>(x, y, um, n_lo + LO0 - C);
+        if constexpr (TWO) {
+          lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
+          xform_gen<LOGV, true, M1>(x, y, um, n_lo + LO1 - C);
+        }
+      } else {
+        const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
+        const uint32_t ym = ymask_of(pc, a.n);
+        xform_xz<LOGV, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
+        if constexpr (TWO) {
+          lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
+          xform_xz<LOGV, M1>(x, y, layout_codes<LOGV>(pc, LO1, LO1, LO0, C, n_lo));
+        }
+        apply_phase<true, LOGV>(x, y, cbase | tf, ym, offf);
       }
-      apply_phase<true, LOGV>(x, y, cbase | tf, ym, offf);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         ax[i] += x[i];
@@ -582,19 +614,19 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   }
 }
 
-template <int TB, int N_HI, bool H16>
+template <int TB, int N_HI, bool H16, bool GEN = false>
 hipError_t launch_hi_n(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st) {
   const int nthr = 1 << (TB - 5);
   const size_t lds = hi_lds_bytes(g);
   const unsigned grid = (unsigned)((g.R << (g.n_lo - g.c)) * a.nsplit);
   if (adjoint) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, true, H16>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, true, H16, GEN>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_hi<TB, N_HI, true, H16><<<grid, nthr, lds, st>>>(a);
+    k_stage_hi<TB, N_HI, true, H16, GEN><<<grid, nthr, lds, st>>>(a);
   } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, false, H16>),
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, false, H16, GEN>),
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_stage_hi<TB, N_HI, false, H16><<<grid, nthr, lds, st>>>(a);
+    k_stage_hi<TB, N_HI, false, H16, GEN><<<grid, nthr, lds, st>>>(a);
   }
   return hipGetLastError();
 }

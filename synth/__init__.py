@@ -116,6 +116,24 @@ def porter_thomas_freqs_torch(seed: int, B: int, D: int, weights, shots: int, de
     return out
 
 
+def haar_unitaries_2x2(rng: np.random.Generator, K: int) -> np.ndarray:
+    """K Haar-random 2x2 unitaries ``[K][2][2]`` complex128 (QR of a complex Gaussian with the
+    phases of R's diagonal moved into Q): single-qubit readout rotations of general local
+    settings."""
+    z = rng.standard_normal((K, 2, 2)) + 1j * rng.standard_normal((K, 2, 2))
+    out = np.empty_like(z)
+    for k in range(K):
+        q, r = np.linalg.qr(z[k])
+        out[k] = q * (np.diag(r) / np.abs(np.diag(r)))
+    return out
+
+
+def random_general_settings(rng: np.random.Generator, B: int, N: int, K: int) -> np.ndarray:
+    """Settings ``[B][N]`` uint8 with codes uniform over the three Pauli bases and ``K`` table
+    entries (codes ``3 .. 3+K-1``)."""
+    return rng.integers(0, 3 + K, size=(B, N)).astype(np.uint8)
+
+
 def poisson_freqs_torch(seed: int, probs, shots: int):
     """Frequencies ``Poisson(shots * p) / shots`` of given per-setting probabilities ``probs``
     (a device tensor ``[B][D]``), drawn with torch's seeded generator on the same device: the
