@@ -359,6 +359,18 @@ def main():
             tms = (time.perf_counter() - t0) * 1e3
             extras[f"{name}_path_ms"] = round(tms, 1)
             extras[f"{name}_speedup_vs_plain"] = round(plain_ms / tms, 2)
+        # general local settings: three Haar 2x2 unitaries besides the Pauli bases (codes 0..5),
+        # one fused backward on the same atoms and frequencies
+        grng = synth.make_rng(seed + 17)
+        table = torch.from_numpy(synth.haar_unitaries_2x2(grng, 3)).to(dev)
+        gset = torch.from_numpy(synth.random_general_settings(grng, B, n, 3)).to(dev)
+        ginst = api.Instance(inst.atoms, inst.weights, gset, freqs, unitaries=table)
+        api.qst_backward(h, [ginst], loss=api.LOSS_CE, eps=1e-8, out=[grad])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.qst_backward(h, [ginst], loss=api.LOSS_CE, eps=1e-8, out=[grad])
+        torch.cuda.synchronize()
+        extras["general_settings_backward_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
         # atom step (eq. pi-update): response of one replaced atom on top of p_t, with the loss,
         # against the full forward (probabilities and loss of all R atoms)
         def med3(fn):
