@@ -130,7 +130,15 @@ typedef enum {
  *             >= 3 + n_unitaries act as the identity and raise the device flag.
  *             Supported on QST_PATH_BUTTERFLY_F32 (and AUTO), one 2x2 per qubit and
  *             setting instead of the Pauli butterflies.
- *   n_unitaries 1..253 when unitaries is given, else ignored                   */
+ *   n_unitaries 1..253 when unitaries is given, else ignored
+ *   freqs_rowptr  NULL: freqs is dense [B][D].  Otherwise the frequencies are sparse
+ *             (CSR, for few shots per setting): freqs holds the freqs_nnz non-zero
+ *             values, freqs_index [freqs_nnz] int32 their outcomes u (strictly
+ *             ascending within a row, 0 <= u < D) and freqs_rowptr [B+1] int64 the
+ *             row starts (freqs_rowptr[0] = 0, freqs_rowptr[B] = freqs_nnz), all on
+ *             the device.  Outcomes outside a row hold zero.  Malformed index data
+ *             cannot make a kernel read or write outside these arrays or its own
+ *             buffers; out-of-range outcomes are dropped.                       */
 typedef struct {
   int32_t n_qubits;
   int32_t rank;
@@ -142,6 +150,9 @@ typedef struct {
   const float* freqs;
   const void* probs_base;
   const double* unitaries;
+  const int64_t* freqs_rowptr;
+  const int32_t* freqs_index;
+  int64_t freqs_nnz;
   int32_t n_unitaries;
 } qst_instance;
 

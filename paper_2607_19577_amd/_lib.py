@@ -42,6 +42,9 @@ class QstInstance(ctypes.Structure):
         ("freqs", ctypes.c_void_p),
         ("probs_base", ctypes.c_void_p),
         ("unitaries", ctypes.c_void_p),
+        ("freqs_rowptr", ctypes.c_void_p),
+        ("freqs_index", ctypes.c_void_p),
+        ("freqs_nnz", ctypes.c_int64),
         ("n_unitaries", ctypes.c_int32),
     ]
 

@@ -95,7 +95,9 @@ class Instance:
     """One tomography instance: atoms [R][D] complex, weights [R] float64,
     settings [B][N] uint8 (X=0, Y=1, Z=2), freqs [B][D] float32 (optional),
     probs_base [B][D] of the path's real type (optional: p = probs_base + the atoms' part),
-    unitaries [K][2][2] complex128 (optional: settings codes c >= 3 apply unitaries[c - 3])."""
+    unitaries [K][2][2] complex128 (optional: settings codes c >= 3 apply unitaries[c - 3]),
+    freqs_csr (rowptr int64 [B+1], index int32 [nnz], values float32 [nnz]) in place of freqs for
+    sparse frequencies."""
 
     atoms: torch.Tensor
     weights: torch.Tensor
@@ -104,6 +106,7 @@ class Instance:
     settings_per_batch: int = 0  # 0: library default
     probs_base: Optional[torch.Tensor] = None
     unitaries: Optional[torch.Tensor] = None
+    freqs_csr: Optional[tuple] = None
 
     @property
     def shape(self):
@@ -126,6 +129,15 @@ class Instance:
             raise ValueError("atoms must be [R][2^N] and weights [R]")
         if self.freqs is not None and tuple(self.freqs.shape) != (B, 1 << N):
             raise ValueError("freqs must be [B][2^N]")
+        csr = self.freqs_csr
+        if csr is not None:
+            if self.freqs is not None:
+                raise ValueError("give freqs or freqs_csr, not both")
+            rp, ix, vals = csr
+            if (rp.dtype != torch.int64 or ix.dtype != torch.int32 or vals.dtype != torch.float32
+                    or rp.shape != (B + 1,) or ix.dim() != 1 or vals.shape != ix.shape
+                    or not (rp.is_contiguous() and ix.is_contiguous() and vals.is_contiguous())):
+                raise ValueError("freqs_csr must be (rowptr int64 [B+1], index int32 [nnz], values float32 [nnz])")
         pb = self.probs_base
         if pb is not None and (pb.dtype != _real_of(path) or not pb.is_contiguous() or tuple(pb.shape) != (B, 1 << N)):
             raise ValueError("probs_base must be contiguous [B][2^N] of the path's real type")
@@ -133,11 +145,14 @@ class Instance:
         if u is not None and (u.dtype != torch.complex128 or not u.is_contiguous() or u.dim() != 3
                               or tuple(u.shape[1:]) != (2, 2)):
             raise ValueError("unitaries must be contiguous [K][2][2] complex128")
+        fptr = self.freqs.data_ptr() if self.freqs is not None else (csr[2].data_ptr() if csr is not None else None)
         return QstInstance(N, R, B, int(self.settings_per_batch), self.atoms.data_ptr(), self.weights.data_ptr(),
-                           self.settings.data_ptr(),
-                           None if self.freqs is None else self.freqs.data_ptr(),
+                           self.settings.data_ptr(), fptr,
                            None if pb is None else pb.data_ptr(),
-                           None if u is None else u.data_ptr(), 0 if u is None else int(u.shape[0]))
+                           None if u is None else u.data_ptr(),
+                           None if csr is None else csr[0].data_ptr(), None if csr is None else csr[1].data_ptr(),
+                           0 if csr is None else int(csr[1].numel()),
+                           0 if u is None else int(u.shape[0]))
 
 
 def _structs(insts: Sequence[Instance], path: int):

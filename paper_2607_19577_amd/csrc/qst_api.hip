@@ -235,7 +235,7 @@ int default_S(const Geometry& g) {
 }
 
 struct WsLayout {
-  size_t pc, um, X, W, part, lvl1, sums, tan, gneg, split, total;
+  size_t pc, um, cptr, X, W, part, lvl1, sums, tan, gneg, split, total;
 };
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -254,6 +254,8 @@ WsLayout layout_ws(const Geometry& g, int S, qst_path path, bool with_gneg, size
   o = al256(o + (size_t)g.B * 8);
   L.um = o;
   if (g.gen) o = al256(o + (size_t)g.B * g.n * 8 * sizeof(float));
+  L.cptr = o;
+  if (g.sparse) o = al256(o + ((size_t)g.B * (pass_path(path) ? 1 : (1ull << g.n_hi)) + 1) * 8);
   L.X = o;
   if (g.n_hi > 0 || pass_path(path)) o = al256(o + vec);
   L.W = o;
@@ -308,6 +310,13 @@ qst_status validate_instance(qst_handle* h, const qst_instance& in, qst_path pat
   if (!aligned(in.atoms, ea) || !aligned(in.weights, 8) || (in.freqs && !aligned(in.freqs, 4)) ||
       (in.probs_base && !aligned(in.probs_base, (size_t)elem_of(path))))
     return set_err(h, QST_ERR_ALIGN, "atoms/weights/freqs/probs_base not aligned to their element size");
+  if (in.freqs_rowptr) {
+    if (!in.freqs_index || !in.freqs) return set_err(h, QST_ERR_INVALID_ARG, "sparse frequencies need freqs and freqs_index");
+    if (in.freqs_nnz < 0 || in.freqs_nnz > (long long)in.n_settings << in.n_qubits)
+      return set_err(h, QST_ERR_SHAPE, "freqs_nnz must be in 0..B*D");
+    if (!aligned(in.freqs_rowptr, 8) || !aligned(in.freqs_index, 4))
+      return set_err(h, QST_ERR_ALIGN, "freqs_rowptr/freqs_index not aligned to their element size");
+  }
   if (in.unitaries) {
     if (path != QST_PATH_BUTTERFLY_F32)
       return set_err(h, QST_ERR_UNSUPPORTED, "general local settings run on QST_PATH_BUTTERFLY_F32");
@@ -334,6 +343,12 @@ struct RunSpec {
   int S_override;
 };
 
+// Per-instance options that change kernels or workspace: general settings, sparse data.
+void mark(Geometry& g, const qst_instance& in) {
+  g.gen = in.unitaries != nullptr;
+  g.sparse = in.freqs_rowptr != nullptr;
+}
+
 // Settings per batch of one instance: the override, else the caller's choice, the
 // autotuned value or the default, in that order.
 int batch_size(const qst_handle* h, const Geometry& g, const qst_instance& in, qst_path path, int S_override) {
@@ -350,7 +365,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   Geometry g;
   qst_status st = make_geometry(h, in.n_qubits, in.rank, in.n_settings, path, g);
   if (st != QST_OK) return st;
-  g.gen = in.unitaries != nullptr;
+  mark(g, in);
   const int S = batch_size(h, g, in, path, rs.S_override);
   set_grid(h, g, S);
   const WsLayout L = layout_ws(g, S, path, false, ws_base);
@@ -367,11 +382,15 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   hipStream_t s = h->stream;
 
   float* um = g.gen ? reinterpret_cast<float*>(ws + L.um) : nullptr;
+  long long* cptr = g.sparse ? reinterpret_cast<long long*>(ws + L.cptr) : nullptr;
   prof_begin(h, PK_DECODE);
   if (g.gen)
     QST_HIP(qst::launch_decode_general(in.settings, g.B, g.n, in.unitaries, in.n_unitaries, um, pc, h->dflag, s));
   else
     QST_HIP(qst::launch_decode(in.settings, g.B, g.n, pc, h->dflag, s));
+  if (g.sparse)
+    QST_HIP(qst::launch_chunk_ptr(reinterpret_cast<const long long*>(in.freqs_rowptr), in.freqs_index,
+                                  in.freqs_nnz, g.B, pass_path(path) ? 1 : (1 << g.n_hi), 1 << g.n_lo, cptr, s));
   prof_end(h);
   const bool want_loss = rs.grad_p == nullptr && rs.loss_kind != QST_LOSS_NONE;
   const long long nslots = nslots_of(g, path);
@@ -379,6 +398,9 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   qst::LoArgs la{};
   la.pc = pc;
   la.um = um;
+  la.fidx = g.sparse ? in.freqs_index : nullptr;
+  la.fchunk = cptr;
+  la.fnnz = in.freqs_nnz;
   la.alpha = in.weights;
   la.freqs = in.freqs;
   la.grad_p = rs.grad_p;
@@ -530,7 +552,7 @@ bool batchable(const Geometry& g, qst_path path) {
 
 struct BatchLayout {
   Geometry g;  // largest rank of the batch; grid of the fused launch
-  std::vector<size_t> pc, W, part;
+  std::vector<size_t> pc, W, part, cptr;
   size_t total = 0;
 };
 
@@ -552,6 +574,7 @@ qst_status batch_layout(qst_handle* h, const std::vector<const RunSpec*>& rs, bo
   L.pc.clear();
   L.W.clear();
   L.part.clear();
+  L.cptr.clear();
   for (const RunSpec* r : rs) {
     const qst_instance& in = *r->in;
     const size_t D = (size_t)1 << n;
@@ -561,6 +584,8 @@ qst_status batch_layout(qst_handle* h, const std::vector<const RunSpec*>& rs, bo
     if (adjoint) o = al256(o + (size_t)in.n_settings * in.rank * D * 2 * (L.g.h16 ? 2 : elem));
     L.part.push_back(o);
     o = al256(o + (size_t)(in.rank + 1) * L.g.grid_lo * 8);
+    L.cptr.push_back(o);
+    if (in.freqs_rowptr) o = al256(o + ((size_t)in.n_settings + 1) * 8);
   }
   L.total = o;
   return QST_OK;
@@ -606,6 +631,10 @@ qst_status run_batch(qst_handle* h, const std::vector<const RunSpec*>& rs) {
     const qst_instance& in = *r.in;
     uint64_t* pc = reinterpret_cast<uint64_t*>(ws + L.pc[k]);
     double* part = reinterpret_cast<double*>(ws + L.part[k]);
+    long long* cptr = in.freqs_rowptr ? reinterpret_cast<long long*>(ws + L.cptr[k]) : nullptr;
+    if (cptr)
+      QST_HIP(qst::launch_chunk_ptr(reinterpret_cast<const long long*>(in.freqs_rowptr), in.freqs_index, in.freqs_nnz,
+                                    in.n_settings, 1, 1 << n, cptr, s));
     db.begin[k] = chunks;
     db.settings[k] = in.settings;
     db.pc[k] = pc;
@@ -619,6 +648,9 @@ qst_status run_batch(qst_handle* h, const std::vector<const RunSpec*>& rs) {
     la.grad_p = r.grad_p;
     la.probs = r.probs;
     la.pbase = in.probs_base;
+    la.fidx = cptr ? in.freqs_index : nullptr;
+    la.fchunk = cptr;
+    la.fnnz = in.freqs_nnz;
     la.gneg = nullptr;
     la.part = (want_loss || adjoint) ? part : nullptr;
     la.nslots = L.g.grid_lo;
@@ -712,7 +744,7 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
       Geometry g;
       qst_status st = make_geometry(h, r->in->n_qubits, r->in->rank, r->in->n_settings, r->path, g);
       if (st != QST_OK) return st;
-      g.gen = r->in->unitaries != nullptr;
+      mark(g, *r->in);
       const int S = batch_size(h, g, *r->in, r->path, 0);
       set_grid(h, g, S);
       *need = std::max(*need, layout_ws(g, S, r->path, false).total);
@@ -927,7 +959,7 @@ qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_pat
     Geometry g;
     st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, path, g);
     if (st != QST_OK) return st;
-    g.gen = inst[i].unitaries != nullptr;
+    mark(g, inst[i]);
     int S = default_S(g);
     if (h->device < 0) continue;
     if (autotune && !pass_path(path) && g.n_hi > 0) {
@@ -1129,7 +1161,7 @@ qst_status qst_atom_trial(qst_handle* h, const qst_instance* inst, int r, const 
   Geometry g;
   st = make_geometry(h, inst->n_qubits, 2, inst->n_settings, path, g);
   if (st != QST_OK) return st;
-  g.gen = inst->unitaries != nullptr;
+  mark(g, *inst);
   st = device_gate(h);
   if (st != QST_OK) return st;
 
@@ -1219,7 +1251,8 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
   if (st != QST_OK) return st;
   st = make_geometry(h, n, 1, B, path, g1);
   if (st != QST_OK) return st;
-  gR.gen = g1.gen = inst->unitaries != nullptr;
+  mark(gR, *inst);
+  mark(g1, *inst);
   const int k_max = (int)std::min<long long>(n_lanczos, D);
   hipStream_t s = h->stream;
 

@@ -26,6 +26,7 @@ struct Geometry {
   int split_adj; // work-groups per adjoint tile at batch size S (partial-sum slices in the workspace)
   bool h16;      // the setting-batch intermediates X and W are stored in BF16
   bool gen;      // general local settings: one 2x2 matrix per (setting, qubit) from the decode
+  bool sparse;   // sparse (CSR) frequencies: chunk pointers in the workspace
 };
 
 struct LoArgs {
@@ -39,6 +40,11 @@ struct LoArgs {
   void* probs;                // [B][D] or null
   const void* pbase;          // [B][D] or null: base probabilities added to p
   const float* um;            // general settings: [B][n][8] matrices by index bit (else null)
+  // sparse frequencies (freqs then holds the non-zero values): fidx [nnz] outcomes, fchunk
+  // [B * 2^n_hi + 1] the first non-zero of each (setting, high index) chunk; null: dense
+  const int* fidx;
+  const long long* fchunk;
+  long long fnnz;
   void* gneg;                 // [B][D] or null: receives -dL/dp
   double* part;               // [(R+1)][nslots]: row 0 loss, rows 1..R weight gradient
   long long nslots;
@@ -128,6 +134,10 @@ hipError_t launch_stage_lo(const Geometry& g, const LoBatch& m, bool adjoint, hi
 hipError_t launch_stage_hi(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_sum_settings(const Geometry& g, const void* W, int S, void* grad, int first, hipStream_t st);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
+// Sparse frequencies: cptr[b * nh + h] = first non-zero of row b with outcome >= h * U
+// (rows from rowptr, outcomes in idx), cptr[B * nh] = nnz; every entry clamped to [0, nnz].
+hipError_t launch_chunk_ptr(const long long* rowptr, const int* idx, long long nnz, int B, int nh, int U,
+                            long long* cptr, hipStream_t st);
 // General local settings: per (setting, qubit) the normalised 2x2 matrix (Pauli codes
 // 0..2 or unitaries[code - 3]) as 8 floats at um[(b * N + index bit) * 8]; pc gets code 0
 // for every qubit.  Codes >= 3 + K raise the flag and apply the identity.

@@ -77,6 +77,48 @@ hipError_t launch_decode_general(const uint8_t* settings, int B, int N, const do
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ sparse frequencies
+__device__ __forceinline__ long long clamp_ll(long long v, long long lo, long long hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// First position in [lo, hi) whose outcome is >= target (idx ascending within a row).
+__device__ __forceinline__ long long lower_bound_idx(const int* __restrict__ idx, long long lo, long long hi,
+                                                     long long target) {
+  while (lo < hi) {
+    const long long mid = lo + ((hi - lo) >> 1);
+    if ((long long)idx[mid] < target)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_chunk_ptr(const long long* __restrict__ rowptr, const int* __restrict__ idx, long long nnz, int B,
+                            int nh, int U, long long* __restrict__ cptr) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long n = (long long)B * nh;
+  if (t > n) return;
+  if (t == n) {
+    cptr[n] = nnz;
+    return;
+  }
+  const int b = (int)(t / nh);
+  const int hh = (int)(t - (long long)b * nh);
+  const long long lo = clamp_ll(rowptr[b], 0, nnz);
+  const long long hi = clamp_ll(rowptr[b + 1], lo, nnz);
+  cptr[t] = lower_bound_idx(idx, lo, hi, (long long)hh * U);
+}
+
+hipError_t launch_chunk_ptr(const long long* rowptr, const int* idx, long long nnz, int B, int nh, int U,
+                            long long* cptr, hipStream_t st) {
+  const long long n = (long long)B * nh + 1;
+  const int bs = 256;
+  k_chunk_ptr<<<(unsigned)((n + bs - 1) / bs), bs, 0, st>>>(rowptr, idx, nnz, B, nh, U, cptr);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ fill
 __global__ void k_fill(uint32_t* p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
@@ -690,14 +732,29 @@ __global__ __launch_bounds__(256) void k_plain_point(const LoArgs a, float2* __r
     if (a.grad_p) {
       g = reinterpret_cast<const float*>(a.grad_p)[gi];
     } else if (a.loss_kind == 0) {
-      const double f = (double)a.freqs[gi];
+      double f = 0.0;
+      if (a.fidx) {  // sparse: row b's non-zeros are [fchunk[b], fchunk[b + 1])
+        const long long e0 = a.fchunk[b], e1 = a.fchunk[b + 1] > e0 ? a.fchunk[b + 1] : e0;
+        const long long e = lower_bound_idx(a.fidx, e0, e1, u);
+        if (e < e1 && (long long)a.fidx[e] == u) f = (double)a.freqs[e];
+      } else {
+        f = (double)a.freqs[gi];
+      }
       if (f > 0.0) {
         const double piv = (double)p / Bd + a.eps;
         loss = -(f / Bd) * log(piv);
         g = (float)(-(f / Bd) / piv / Bd);
       }
     } else if (a.loss_kind == 1) {
-      const double rr = ((double)p - (double)a.freqs[gi]) / Bd;
+      double f = 0.0;
+      if (a.fidx) {
+        const long long e0 = a.fchunk[b], e1 = a.fchunk[b + 1] > e0 ? a.fchunk[b + 1] : e0;
+        const long long e = lower_bound_idx(a.fidx, e0, e1, u);
+        if (e < e1 && (long long)a.fidx[e] == u) f = (double)a.freqs[e];
+      } else {
+        f = (double)a.freqs[gi];
+      }
+      const double rr = ((double)p - f) / Bd;
       loss = 0.5 * rr * rr;
       g = (float)(rr / Bd);
     }

@@ -255,7 +255,7 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
     const uint32_t vo0 = voff(a, CBI);
 #pragma unroll
     for (int i = 0; i < V; ++i) ld_cs<H16_IN>(bx[i], by[i], rs, vo0, (uint32_t)(i << LO0) * CBI);
-    if (a.grad_p != nullptr || a.loss_kind != 2) {
+    if (a.grad_p != nullptr || (a.loss_kind != 2 && a.fidx == nullptr)) {
       const long long row = (long long)(a.b0 + s) * a.D + ((long long)h << N_LO);
 #pragma unroll
       for (int j = 0; j < NPF; ++j) {
@@ -309,6 +309,24 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
     const long long row = (long long)b * D + ((long long)h << N_LO);
     const T* gp = reinterpret_cast<const T*>(a.grad_p);
     const T* pbp = reinterpret_cast<const T*>(a.pbase);
+    // Sparse frequencies: this chunk's observed outcomes are scattered into the g row
+    // (zero elsewhere); each outcome's thread reads its value before writing g there.
+    // Every thread has passed the barrier above, so no read of the previous chunk's g
+    // is pending.  Outcomes outside the chunk are dropped.
+    const bool sparse = a.fidx != nullptr && gp == nullptr && a.loss_kind != 2;
+    if (sparse) {
+      for (int u = tid; u < U; u += nthr) gb[pad32(u)] = T(0);
+      __syncthreads();
+      const long long ci = (long long)b * (1ll << a.n_hi) + h;
+      const long long e0 = a.fchunk[ci];
+      long long e1 = a.fchunk[ci + 1];
+      if (e1 < e0) e1 = e0;
+      for (long long e = e0 + tid; e < e1; e += nthr) {
+        const long long uu = (long long)a.fidx[e] - ((long long)h << N_LO);
+        if (uu >= 0 && uu < U) gb[pad32((int)uu)] = (T)a.freqs[e];
+      }
+      __syncthreads();
+    }
     // One outcome u of the chunk: p (atom sum, scale, base), loss term, sensitivity.
     // d is the data value of the outcome (dL/dp in the generic mode, else the frequency).
     auto outcome = [&](int u, T d, T pb) __attribute__((always_inline)) {
@@ -362,7 +380,9 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
         dg[jj] = 0;
         bg[jj] = 0;
         if (u < U) {
-          if (row_data) {
+          if (sparse) {
+            dg[jj] = gb[pad32(u)];
+          } else if (row_data) {
             if (jj < NPF && j0 == 0)
               dg[jj] = fv[jj < NPF ? jj : 0];
             else

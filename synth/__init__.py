@@ -134,6 +134,16 @@ def random_general_settings(rng: np.random.Generator, B: int, N: int, K: int) ->
     return rng.integers(0, 3 + K, size=(B, N)).astype(np.uint8)
 
 
+def dense_to_csr(f: np.ndarray):
+    """``(rowptr int64 [B+1], index int32 [nnz], values float32 [nnz])`` of the non-zero entries of a
+    ``[B][D]`` frequency array, outcomes ascending within each row."""
+    f = np.asarray(f, dtype=np.float32)
+    rows, cols = np.nonzero(f)
+    rowptr = np.zeros(f.shape[0] + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    return np.cumsum(rowptr).astype(np.int64), cols.astype(np.int32), f[rows, cols].astype(np.float32)
+
+
 def poisson_freqs_torch(seed: int, probs, shots: int):
     """Frequencies ``Poisson(shots * p) / shots`` of given per-setting probabilities ``probs``
     (a device tensor ``[B][D]``), drawn with torch's seeded generator on the same device: the
