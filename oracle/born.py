@@ -110,19 +110,20 @@ def probs_axis(atoms, weights, settings, rows=None, table=None) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- atom step (response update)
-def atom_response_axis(psi, settings, rows=None) -> np.ndarray:
+def atom_response_axis(psi, settings, rows=None, table=None) -> np.ndarray:
     """One-atom response ``a(psi)[b, u] = |(V_b psi)_u|^2`` per setting (eq. atom-response in
     the per-setting layout, i.e. ``B`` times the stacked ``a_m(psi)``)."""
     psi = np.asarray(psi, dtype=np.complex128)
-    return probs_axis(psi[None, :], np.ones(1), settings, rows)
+    return probs_axis(psi[None, :], np.ones(1), settings, rows, table=table)
 
 
-def atom_trial_probs(atoms, weights, settings, r, psi_trial, p_t, rows=None) -> np.ndarray:
+def atom_trial_probs(atoms, weights, settings, r, psi_trial, p_t, rows=None, table=None) -> np.ndarray:
     """Probabilities after atom ``r`` is replaced by ``psi_trial`` (eq. atom-trial), by the
     response update of eq. pi-update: ``p~ = p_t + alpha_r d`` with the response difference
     ``d = a(psi_trial) - a(psi_r)``.  ``p_t`` holds the current probabilities of the rows used."""
     alpha_r = float(np.asarray(weights, dtype=np.float64)[r])
-    d = atom_response_axis(psi_trial, settings, rows) - atom_response_axis(np.asarray(atoms)[r], settings, rows)
+    d = (atom_response_axis(psi_trial, settings, rows, table)
+         - atom_response_axis(np.asarray(atoms)[r], settings, rows, table))
     return np.asarray(p_t, dtype=np.float64) + alpha_r * d
 
 

@@ -14,30 +14,35 @@ from . import api
 
 
 class BornMap(torch.autograd.Function):
-    """probs[b, u] = sum_r alpha_r |(V_b psi_r)_u|^2  (per-setting Born probabilities)."""
+    """probs[b, u] = sum_r alpha_r |(V_b psi_r)_u|^2  (per-setting Born probabilities).
+    ``unitaries`` (optional) holds the 2x2 matrices of settings codes >= 3."""
 
     @staticmethod
-    def forward(ctx, atoms, weights, settings, handle, path):
-        inst = api.Instance(atoms.detach().contiguous(), weights.detach().contiguous(), settings)
+    def forward(ctx, atoms, weights, settings, handle, path, unitaries):
+        inst = api.Instance(atoms.detach().contiguous(), weights.detach().contiguous(), settings, unitaries=unitaries)
         probs, _ = api.qst_forward(handle, [inst], want_probs=True, path=path)
         ctx.save_for_backward(atoms, weights, settings)
-        ctx.handle, ctx.path = handle, path
+        ctx.handle, ctx.path, ctx.unitaries = handle, path, unitaries
         return probs[0]
 
     @staticmethod
     def backward(ctx, grad_probs):
         atoms, weights, settings = ctx.saved_tensors
-        inst = api.Instance(atoms.detach().contiguous(), weights.detach().contiguous(), settings)
+        inst = api.Instance(atoms.detach().contiguous(), weights.detach().contiguous(), settings,
+                            unitaries=ctx.unitaries)
         _, ag, wg = api.qst_backward(ctx.handle, [inst], grad_p=[grad_probs.contiguous()], path=ctx.path)
-        return 2 * ag[0], wg[0], None, None, None
+        return 2 * ag[0], wg[0], None, None, None, None
 
 
 class FusedLoss(torch.autograd.Function):
-    """Loss (CE or LS on the stacked probabilities) with its gradients from one fused pass."""
+    """Loss (CE or LS on the stacked probabilities) with its gradients from one fused pass.
+    ``freqs`` is a dense [B][D] tensor or a CSR triple (rowptr, index, values)."""
 
     @staticmethod
-    def forward(ctx, atoms, weights, settings, freqs, handle, loss, eps, path):
-        inst = api.Instance(atoms.detach().contiguous(), weights.detach().contiguous(), settings, freqs)
+    def forward(ctx, atoms, weights, settings, freqs, handle, loss, eps, path, unitaries):
+        dense = freqs if isinstance(freqs, torch.Tensor) else None
+        inst = api.Instance(atoms.detach().contiguous(), weights.detach().contiguous(), settings, dense,
+                            unitaries=unitaries, freqs_csr=None if dense is not None else tuple(freqs))
         lt, ag, wg = api.qst_backward(handle, [inst], loss=loss, eps=eps, path=path)
         ctx.save_for_backward(ag[0], wg[0])
         return lt[0]
@@ -45,12 +50,13 @@ class FusedLoss(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         ag, wg = ctx.saved_tensors
-        return 2 * ag * grad_out.to(ag.real.dtype), wg * grad_out, None, None, None, None, None, None
+        return 2 * ag * grad_out.to(ag.real.dtype), wg * grad_out, None, None, None, None, None, None, None
 
 
-def born_map(atoms, weights, settings, handle, path=api.PATH_AUTO):
-    return BornMap.apply(atoms, weights, settings, handle, path)
+def born_map(atoms, weights, settings, handle, path=api.PATH_AUTO, unitaries=None):
+    return BornMap.apply(atoms, weights, settings, handle, path, unitaries)
 
 
-def fused_loss(atoms, weights, settings, freqs, handle, loss=api.LOSS_CE, eps=1e-8, path=api.PATH_AUTO):
-    return FusedLoss.apply(atoms, weights, settings, freqs, handle, loss, eps, path)
+def fused_loss(atoms, weights, settings, freqs, handle, loss=api.LOSS_CE, eps=1e-8, path=api.PATH_AUTO,
+               unitaries=None):
+    return FusedLoss.apply(atoms, weights, settings, freqs, handle, loss, eps, path, unitaries)

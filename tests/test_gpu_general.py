@@ -120,3 +120,69 @@ def test_code_beyond_the_table_raises_the_flag(h):
         api.qst_forward(h, [_inst(c)], want_probs=True)
     torch.cuda.synchronize()
     api.qst_forward(h, [_inst(_case(1671, 6, 2, 4))], want_probs=True)  # the flag was cleared
+
+
+def test_autograd_with_general_settings_and_sparse_data(h):
+    """torch.autograd through the general-settings forward (caller's dL/dp) and the fused loss on
+    sparse frequencies, against the oracle's gradients (torch's complex gradient is twice the
+    conjugate-Wirtinger one)."""
+    from paper_2607_19577_amd.autograd import born_map, fused_loss
+
+    c = _case(1680, 8, 3, 6, shots=60)
+    a = torch.from_numpy(c["atoms"]).to(DEV).requires_grad_(True)
+    w = torch.from_numpy(c["weights"]).to(DEV).requires_grad_(True)
+    s = torch.from_numpy(c["settings"]).to(DEV)
+    table = torch.from_numpy(c["table"]).to(DEV)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(3)
+    cw = torch.randn((6, 256), generator=gen, device=DEV)
+    (born_map(a, w, s, h, unitaries=table) * cw).sum().backward()
+    torch.cuda.synchronize()
+    gar, gwr = born.gradients_axis(c["atoms"].astype(np.complex128), c["weights"], c["settings"],
+                                   cw.cpu().numpy().astype(np.float64), table=c["table"])
+    ga = a.grad.cpu().numpy() / 2
+    for r in range(3):
+        assert close(ga[r], gar[r], 1e-5), (r, rel(ga[r], gar[r]))
+    assert close(w.grad.cpu().numpy(), gwr, 1e-5)
+    a.grad = None
+    w.grad = None
+    rp, ix, vals = synth.dense_to_csr(c["freqs"])
+    csr = (torch.from_numpy(rp).to(DEV), torch.from_numpy(ix).to(DEV), torch.from_numpy(vals).to(DEV))
+    L = fused_loss(a, w, s, csr, h, unitaries=table)
+    L.backward()
+    torch.cuda.synchronize()
+    Lr, _, gar, gwr = born.forward_backward(c["atoms"].astype(np.complex128), c["weights"], c["settings"],
+                                            c["freqs"].astype(np.float64), born.LOSS_CE, 1e-8, table=c["table"])
+    assert abs(float(L.detach()) - Lr) <= 1e-5 * abs(Lr)
+    ga = a.grad.cpu().numpy() / 2
+    for r in range(3):
+        assert close(ga[r], gar[r], 1e-5), (r, rel(ga[r], gar[r]))
+    assert close(w.grad.cpu().numpy(), gwr, 1e-5)
+
+
+def test_atom_trial_and_solve_with_general_settings(h):
+    """The atom-step update and the iteration carry the unitary table through every call."""
+    from paper_2607_19577_amd import api
+
+    c = _case(1690, 9, 3, 8, shots=3000)
+    inst = _inst(c)
+    p_t = born.probs_axis(c["atoms"].astype(np.complex128), c["weights"], c["settings"], table=c["table"])
+    trial = synth.haar_atoms(synth.make_rng(1691), 1, 512, dtype=np.complex64)[0]
+    probs, lt = api.qst_atom_trial(h, inst, 1, torch.from_numpy(trial).to(DEV),
+                                   torch.from_numpy(p_t.astype(np.float32)).to(DEV), loss=api.LOSS_CE, eps=1e-8)
+    torch.cuda.synchronize()
+    pr = born.atom_trial_probs(c["atoms"].astype(np.complex128), c["weights"], c["settings"], 1,
+                               trial.astype(np.complex128), p_t.astype(np.float32).astype(np.float64),
+                               table=c["table"])
+    assert close(probs.cpu().numpy(), pr, 1e-5), rel(probs.cpu().numpy(), pr)
+    v0s = torch.from_numpy(synth.haar_atoms(synth.make_rng(1692), 2, 512, dtype=np.complex128)).to(DEV)
+    prm = api.SolveParams(max_slots=25, t_alpha=5, t_ref=10, rank_max=4, n_lanczos=12, stop_window=0,
+                          oracle_budget=0)
+    res = api.qst_solve(h, inst, prm, v0s)
+    hist = res["history"]
+    assert hist[:, 4].sum() >= 3
+    a = res["atoms"].cpu().numpy().astype(np.complex128)
+    wv = res["weights"].cpu().numpy()
+    p = born.probs_axis(a, wv, c["settings"], table=c["table"])
+    L, _ = born.loss_and_sensitivity(p, c["freqs"].astype(np.float64), 8, born.LOSS_CE, 1e-8)
+    assert abs(L + prm.mu * res["rank"] - hist[-1, 2]) <= 1e-5 * abs(hist[-1, 2])
