@@ -181,9 +181,13 @@ size_t hi_lds_bytes(const Geometry& g) {
 }
 
 // ------------------------------------------------------------------ sum over settings (no high bits)
-// sum_s W[s][e] with four interleaved partial sums (more loads in flight per thread),
-// combined in a fixed order; the single-instance and the batched kernels share it, so
-// both give the same bits.
+// grad[e] (+)= sum_s W[s][e].  A block takes kSumCols consecutive elements; for each,
+// kSumSlices threads sum the settings s = slice, slice + kSumSlices, ... in increasing
+// order, and the slice sums are added in a fixed tree.  The single-instance and the
+// batched kernels share this order, so both give the same bits.
+constexpr int kSumSlices = 8;
+constexpr int kSumCols = 32;
+
 template <typename T, bool H16>
 __device__ __forceinline__ cx<T> w_at(const void* W, long long i) {
   if constexpr (H16) {
@@ -195,43 +199,51 @@ __device__ __forceinline__ cx<T> w_at(const void* W, long long i) {
 }
 
 template <typename T, bool H16>
-__device__ __forceinline__ cx<T> settings_sum(const void* __restrict__ W, int S, long long RD, long long e) {
-  cx<T> a[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  int s = 0;
-  for (; s + 4 <= S; s += 4) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const cx<T> w = w_at<T, H16>(W, (long long)(s + j) * RD + e);
-      a[j].x += w.x;
-      a[j].y += w.y;
-    }
-  }
-  for (int j = 0; s < S; ++s, ++j) {
+__device__ __forceinline__ cx<T> settings_slice(const void* __restrict__ W, int S, long long RD, long long e, int sl) {
+  cx<T> a{0, 0};
+  for (int s = sl; s < S; s += kSumSlices) {
     const cx<T> w = w_at<T, H16>(W, (long long)s * RD + e);
-    a[j].x += w.x;
-    a[j].y += w.y;
+    a.x += w.x;
+    a.y += w.y;
   }
-  return cx<T>{(a[0].x + a[1].x) + (a[2].x + a[3].x), (a[0].y + a[1].y) + (a[2].y + a[3].y)};
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> slice_tree(const cx<T> (*part)[kSumCols], int col) {
+  auto add = [](cx<T> a, cx<T> b) { return cx<T>{a.x + b.x, a.y + b.y}; };
+  const cx<T> p01 = add(part[0][col], part[1][col]), p23 = add(part[2][col], part[3][col]);
+  const cx<T> p45 = add(part[4][col], part[5][col]), p67 = add(part[6][col], part[7][col]);
+  return add(add(p01, p23), add(p45, p67));
 }
 
 template <typename T, bool H16>
-__global__ void k_sum_settings(const void* __restrict__ W, int S, long long RD, cx<T>* __restrict__ grad, int first) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < RD; e += (long long)gridDim.x * blockDim.x) {
-    const cx<T> acc = settings_sum<T, H16>(W, S, RD, e);
-    if (first) {
-      grad[e] = acc;
-    } else {
-      cx<T> x = grad[e];
-      grad[e] = cx<T>{x.x + acc.x, x.y + acc.y};
+__global__ __launch_bounds__(kSumSlices * kSumCols) void k_sum_settings(const void* __restrict__ W, int S, long long RD,
+                                                                        cx<T>* __restrict__ grad, int first) {
+  __shared__ cx<T> part[kSumSlices][kSumCols];
+  const int col = threadIdx.x % kSumCols, sl = threadIdx.x / kSumCols;
+  for (long long e0 = blockIdx.x * (long long)kSumCols; e0 < RD; e0 += (long long)gridDim.x * kSumCols) {
+    const long long e = e0 + col;
+    part[sl][col] = e < RD ? settings_slice<T, H16>(W, S, RD, e, sl) : cx<T>{0, 0};
+    __syncthreads();
+    if (sl == 0 && e < RD) {
+      const cx<T> acc = slice_tree<T>(part, col);
+      if (first) {
+        grad[e] = acc;
+      } else {
+        const cx<T> x = grad[e];
+        grad[e] = cx<T>{x.x + acc.x, x.y + acc.y};
+      }
     }
+    __syncthreads();
   }
 }
 
 hipError_t launch_sum_settings(const Geometry& g, const void* W, int S, void* grad, int first, hipStream_t st) {
   const long long RD = (long long)g.R * g.D;
-  const int bs = 256;
-  long long nb = (RD + bs - 1) / bs;
+  long long nb = (RD + kSumCols - 1) / kSumCols;
   if (nb > 8192) nb = 8192;
+  const int bs = kSumSlices * kSumCols;
   if (g.elem == 4 && g.h16)
     k_sum_settings<float, true><<<(unsigned)nb, bs, 0, st>>>(W, S, RD, reinterpret_cast<float2*>(grad), first);
   else if (g.elem == 4)
@@ -446,20 +458,31 @@ hipError_t launch_decode_batch(const DecodeBatch& b, int* flag, hipStream_t st) 
 }
 
 template <typename T, bool H16>
-__global__ void k_sum_batch(const SumBatch b) {
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < b.total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int k = batch_find(b.begin, b.count, t);
-    const long long e = t - b.begin[k];
-    reinterpret_cast<cx<T>*>(b.grad[k])[e] = settings_sum<T, H16>(b.W[k], b.S[k], b.RD[k], e);
+__global__ __launch_bounds__(kSumSlices * kSumCols) void k_sum_batch(const SumBatch b) {
+  __shared__ cx<T> part[kSumSlices][kSumCols];
+  const int col = threadIdx.x % kSumCols, sl = threadIdx.x / kSumCols;
+  for (long long t0 = blockIdx.x * (long long)kSumCols; t0 < b.total; t0 += (long long)gridDim.x * kSumCols) {
+    const long long t = t0 + col;
+    int k = 0;
+    long long e = 0;
+    if (t < b.total) {
+      k = batch_find(b.begin, b.count, t);
+      e = t - b.begin[k];
+      part[sl][col] = settings_slice<T, H16>(b.W[k], b.S[k], b.RD[k], e, sl);
+    } else {
+      part[sl][col] = cx<T>{0, 0};
+    }
+    __syncthreads();
+    if (sl == 0 && t < b.total) reinterpret_cast<cx<T>*>(b.grad[k])[e] = slice_tree<T>(part, col);
+    __syncthreads();
   }
 }
 
 hipError_t launch_sum_batch(const SumBatch& b, hipStream_t st) {
   if (b.total < 1) return hipSuccess;
-  const int bs = 256;
-  long long nb = (b.total + bs - 1) / bs;
+  long long nb = (b.total + kSumCols - 1) / kSumCols;
   if (nb > 8192) nb = 8192;
+  const int bs = kSumSlices * kSumCols;
   if (b.elem == 4 && b.h16)
     k_sum_batch<float, true><<<(unsigned)nb, bs, 0, st>>>(b);
   else if (b.elem == 4)
