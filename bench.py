@@ -73,16 +73,18 @@ def _cpu_grads(task):
 
     b, r = task
     ga, gw = born.gradients_axis(_CPU["atoms"][r:r + 1], _CPU["w"][r:r + 1], _CPU["s"], _CPU["g"][[b]], rows=[b])
-    return float(gw[0])
+    return ga[0], float(gw[0])
 
 
 def cpu_baseline(atoms, w, s, B, shots, n_sample: int, seed: int):
-    """The FP64 oracle (per-axis tier) on n_sample settings x all atoms: probabilities, loss and
-    sensitivities, then the adjoint, split into (setting, atom) calls over a fork pool."""
+    """The FP64 oracle (per-axis tier) on an instance made of the first n_sample settings, all
+    atoms: probabilities, loss and sensitivities, then the adjoint, split into (setting, atom)
+    calls over a fork pool.  Returns the timing record and the oracle's outputs (frequencies,
+    loss, weight and atom gradients) for the error report of the GPU path on the same sample."""
     from oracle import born
 
-    R = atoms.shape[0]
-    f = synth.porter_thomas_freqs(synth.make_rng(seed), n_sample, atoms.shape[1], synth.dirichlet_weights(
+    R, D = atoms.shape
+    f = synth.porter_thomas_freqs(synth.make_rng(seed), n_sample, D, synth.dirichlet_weights(
         synth.make_rng(seed + 1), 4), shots)
     _CPU.update(atoms=atoms.astype(np.complex128), w=w, s=s[:n_sample])
     tasks = [(b, r) for b in range(n_sample) for r in range(R)]
@@ -91,18 +93,30 @@ def cpu_baseline(atoms, w, s, B, shots, n_sample: int, seed: int):
     t0 = time.perf_counter()
     with ctx.Pool(cores, initializer=_cpu_init) as pool:
         parts = pool.map(_cpu_probs, tasks)
-        p = np.zeros((n_sample, atoms.shape[1]))
+        p = np.zeros((n_sample, D))
         for (b, _), q in zip(tasks, parts):
             p[b] += q
-        _, g = born.loss_and_sensitivity(p, f, B, born.LOSS_CE, 1e-8)
+        loss, g = born.loss_and_sensitivity(p, f, n_sample, born.LOSS_CE, 1e-8)
         _CPU["g"] = g
+    ga = np.zeros((R, D), dtype=np.complex128)
+    gw = np.zeros(R)
     with ctx.Pool(cores, initializer=_cpu_init) as pool:
-        pool.map(_cpu_grads, tasks)
+        for (_, r), (a, x) in zip(tasks, pool.imap(_cpu_grads, tasks)):
+            ga[r] += a
+            gw[r] += x
     dt = time.perf_counter() - t0
-    amps = n_sample * R * atoms.shape[1]
-    return dict(value=amps / dt, unit="amplitudes/s", cores=cores, kind="oracle",
-                sample=f"{n_sample} of {B} settings x {R} atoms x D={atoms.shape[1]}: FP64 per-axis oracle "
-                       f"probabilities, CE loss and sensitivities, adjoint; {dt:.1f} s wall on {cores} processes")
+    amps = n_sample * R * D
+    rec = dict(value=amps / dt, unit="amplitudes/s", cores=cores, kind="oracle",
+               sample=f"{n_sample} of {B} settings x {R} atoms x D={D} (an instance of those settings): "
+                      f"FP64 per-axis oracle probabilities, CE loss and sensitivities, adjoint; {dt:.1f} s "
+                      f"wall on {cores} processes")
+    return rec, dict(freqs=f, loss=float(loss), weight_grad=gw, atom_grad=ga)
+
+
+def _relerr(got, ref) -> float:
+    """Norm-wise relative error ||got - ref|| / ||ref||."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    return float(np.linalg.norm((got - ref).ravel()) / max(np.linalg.norm(ref.ravel()), 1e-300))
 
 
 # ---------------------------------------------------------------- traffic file
@@ -256,10 +270,10 @@ def main():
     s = synth.random_settings(rng, B, n)
     w_true = synth.dirichlet_weights(rng, wl["R_true"])
 
-    cpu = None
+    cpu = cpu_ref = None
     if not args.no_cpu_baseline:
         n_sample = 2 if n >= 18 else min(B, 64 if n <= 12 else 8)
-        cpu = cpu_baseline(atoms, w, s, B, shots, n_sample, seed + 7)
+        cpu, cpu_ref = cpu_baseline(atoms, w, s, B, shots, n_sample, seed + 7)
         print(f"[bench] cpu baseline: {cpu['value']:.3e} amplitudes/s ({cpu['sample']})", file=sys.stderr, flush=True)
 
     if args.batch > 0:
@@ -296,11 +310,16 @@ def main():
     h.profile(True)
     h.profile_read(reset=True)
     torch.cuda.synchronize()
+    # events on the stream the library launches on (torch's current stream) bracket each step
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for i in range(args.steps):
         lt = step()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
     stages = h.profile_read(reset=True)
     h.profile(False)
     ms_per_step = elapsed * 1e3 / args.steps
@@ -335,6 +354,22 @@ def main():
     model_bytes_step = sum((per_launch_bytes[k] or 0) * stages[k][0] for k in per_launch_bytes) / args.steps
 
     extras = {}
+    if cpu_ref is not None:
+        # errors of the timed path against the oracle on the CPU sample (same atoms, weights and
+        # settings; the sample's own frequencies)
+        ns = cpu_ref["freqs"].shape[0]
+        sub = api.Instance(inst.atoms, inst.weights, inst.settings[:ns].contiguous(),
+                           torch.from_numpy(cpu_ref["freqs"]).to(dev))
+        lt_s, ag_s, wg_s = api.qst_backward(h, [sub], loss=api.LOSS_CE, eps=1e-8, path=step_path)
+        torch.cuda.synchronize()
+        tol = 1e-5 if args.path == "butterfly_f32" else 1e-2
+        errs = {"loss": _relerr(float(lt_s[0]), cpu_ref["loss"]),
+                "weight_grad": _relerr(wg_s[0].cpu().numpy(), cpu_ref["weight_grad"]),
+                "atom_grad": _relerr(ag_s[0].cpu().numpy(), cpu_ref["atom_grad"])}
+        extras["errors_vs_oracle"] = {"settings": ns, "norm": "||x - x_oracle|| / ||x_oracle||",
+                                      **{k: float(f"{v:.3e}") for k, v in errs.items()}, "tol": tol,
+                                      "pass": all(v <= tol for v in errs.values())}
+        del sub, lt_s, ag_s, wg_s, cpu_ref
     if not args.no_extras:
         # plain one-pass-per-qubit reference kernel on the same workload (one call)
         torch.cuda.synchronize()
@@ -421,6 +456,9 @@ def main():
                    "settings_per_batch": S},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "step_ms_events": {"median": round(float(np.median(step_ms)), 3),
+                           "iqr": round(float(np.percentile(step_ms, 75) - np.percentile(step_ms, 25)), 3),
+                           "min": round(float(step_ms.min()), 3), "max": round(float(step_ms.max()), 3)},
         "stage_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in stages.items()},
         "model_hbm_bytes_per_step": model_bytes_step,
         "model_GBps_whole_step": round(model_bytes_step / (ms_per_step * 1e-3) / 1e9, 1),

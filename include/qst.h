@@ -74,7 +74,7 @@ typedef enum {
   QST_ERR_UNSUPPORTED = 4, /* valid request this build does not implement     */
   QST_ERR_DEVICE = 5,      /* HIP runtime error (message in qst_last_error)  */
   QST_ERR_OOM = 6,         /* workspace allocation failed                     */
-  QST_ERR_NUMERIC = 7,     /* a kernel raised its device flag (bad code)       */
+  QST_ERR_NUMERIC = 7,     /* a kernel raised its device flag (bad code or table entry) */
   QST_ERR_CAPTURE = 8      /* would allocate while the stream is capturing    */
 } qst_status;
 
@@ -125,9 +125,10 @@ typedef enum {
  *             (row-major, re,im interleaved: 8 doubles each, 8-byte aligned) for
  *             general local product measurements (the paper's descriptor-level
  *             measurement actions): a code c >= 3 applies unitaries[c - 3] to its
- *             qubit before the computational-basis readout.  The matrices are used
- *             as given (unitarity is the caller's; p rows then sum to one).  Codes
- *             >= 3 + n_unitaries act as the identity and raise the device flag.
+ *             qubit before the computational-basis readout.  Each entry must be
+ *             unitary (checked in FP64: columns of unit norm and orthogonal to 1e-6);
+ *             an entry that is not, and codes >= 3 + n_unitaries, act as the
+ *             identity and raise the device flag (QST_ERR_NUMERIC from a later call).
  *             Supported on QST_PATH_BUTTERFLY_F32 (and AUTO), one 2x2 per qubit and
  *             setting instead of the Pauli butterflies.
  *   n_unitaries 1..253 when unitaries is given, else ignored

@@ -281,10 +281,13 @@ qst_status check_flag(qst_handle* h) {
   if (hipEventQuery(h->flag_ev) != hipSuccess) return QST_OK;  // not reached yet: report later
   h->flag_pending = false;
   if (*h->hflag) {
+    const int f = *h->hflag;
     *h->hflag = 0;
     qst::launch_fill(h->dflag, sizeof(int), h->stream);
-    return set_err(h, QST_ERR_NUMERIC,
-                   "a setting held a code outside the Pauli codes and the unitary table (treated as the identity)");
+    std::string msg;
+    if (f & 1) msg = "a setting held a code outside the Pauli codes and the unitary table";
+    if (f & 2) msg += std::string(msg.empty() ? "" : "; ") + "a unitary table entry was not unitary to 1e-6";
+    return set_err(h, QST_ERR_NUMERIC, msg + " (treated as the identity)");
   }
   return QST_OK;
 }

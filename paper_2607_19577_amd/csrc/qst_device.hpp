@@ -127,35 +127,46 @@ __device__ __forceinline__ void xform_xz(T (&x)[1 << LOGV], T (&y)[1 << LOGV], u
   xform_xz_bit<0, LOGV, ACTIVE>(x, y, codes);
 }
 
-// General local settings: register bit K applies the 2x2 complex matrix at
-// um + 8 (qidx0 + K) (a00, a01, a10, a11 as re, im pairs; uniform across the
-// work-group), or its conjugate transpose (ADJ):  a' = m00 a + m01 b, b' = m10 a + m11 b.
-// Sixteen multiply-adds per pair; no phase split and no skipped bits (the decode
-// writes the identity for Z).
+// The per-setting coefficients of general settings are read through the constant address
+// space: their addresses are uniform, so the loads become scalar loads into SGPRs (issued
+// early and batched) instead of one vector load and wait per coefficient.
+using cfptr = const __attribute__((address_space(4))) float*;
+__device__ __forceinline__ cfptr to_const(const float* p) { return (cfptr)(p); }
+
+// A value that is the same in every lane, moved to a scalar register (a uniform branch
+// on it then needs no lane mask).
+__device__ __forceinline__ float uniform_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// General local settings in rotation form.  The decode writes each qubit's matrix as
+// P R diag(1, e): the outcome-side phases P drop out of |phi|^2 and of V^dagger diag(g) V,
+// the input-side phases diag(1, e) of all qubits commute with every rotation and are
+// applied once per element (apply_gphase), and what is left per qubit is the real
+// rotation R = [[c, -s], [s, c]] (adjoint: its transpose, the angle negated).  It is
+// applied as three shears (lifting): a -= t b, b += s a, a -= t b with t = tan(theta/2)
+// and s = sin(theta), theta in [0, pi/2], stored at um + 8 q as (t, s) for index bit q
+// (uniform across the work-group): six multiply-adds per pair, in place, and exact up to
+// one rounding per shear.  The identity (t = s = 0) runs the same code: a branch around
+// it makes the compiler keep both versions of the registers live at the join and spill.
 template <int K, int LOGV, bool ADJ, uint32_t ACTIVE, typename T>
-__device__ __forceinline__ void xform_gen_bit(T (&x)[1 << LOGV], T (&y)[1 << LOGV], const float* um, int qidx0) {
+__device__ __forceinline__ void xform_gen_bit(T (&x)[1 << LOGV], T (&y)[1 << LOGV], cfptr um, int qidx0) {
   if constexpr (K < LOGV) {
     if constexpr ((ACTIVE >> K) & 1u) {
-      const float* m = um + 8 * (qidx0 + K);
-      T m00r = m[0], m00i = m[1], m01r = m[2], m01i = m[3], m10r = m[4], m10i = m[5], m11r = m[6], m11i = m[7];
-      if constexpr (ADJ) {  // conjugate transpose
-        const T t0 = m01r, t1 = m01i;
-        m01r = m10r;
-        m01i = -m10i;
-        m10r = t0;
-        m10i = -t1;
-        m00i = -m00i;
-        m11i = -m11i;
-      }
+      const cfptr m = um + 8 * (qidx0 + K);
+      const T tv = uniform_f32(m[0]), sv = uniform_f32(m[1]);
+      const T nt = ADJ ? tv : -tv;  // -t of the applied angle
+      const T s = ADJ ? -sv : sv;
 #pragma unroll
       for (int i = 0; i < (1 << LOGV); ++i) {
         if (i & (1 << K)) continue;
         const int j = i | (1 << K);
-        const T ax = x[i], ay = y[i], bx = x[j], by = y[j];
-        x[i] = fma(m00r, ax, fma(-m00i, ay, fma(m01r, bx, -m01i * by)));
-        y[i] = fma(m00r, ay, fma(m00i, ax, fma(m01r, by, m01i * bx)));
-        x[j] = fma(m10r, ax, fma(-m10i, ay, fma(m11r, bx, -m11i * by)));
-        y[j] = fma(m10r, ay, fma(m10i, ax, fma(m11r, by, m11i * bx)));
+        x[i] = fma(nt, x[j], x[i]);
+        y[i] = fma(nt, y[j], y[i]);
+        x[j] = fma(s, x[i], x[j]);
+        y[j] = fma(s, y[i], y[j]);
+        x[i] = fma(nt, x[j], x[i]);
+        y[i] = fma(nt, y[j], y[i]);
       }
     }
     xform_gen_bit<K + 1, LOGV, ADJ, ACTIVE>(x, y, um, qidx0);
@@ -163,9 +174,79 @@ __device__ __forceinline__ void xform_gen_bit(T (&x)[1 << LOGV], T (&y)[1 << LOG
 }
 
 template <int LOGV, bool ADJ, uint32_t ACTIVE, typename T>
-__device__ __forceinline__ void xform_gen(T (&x)[1 << LOGV], T (&y)[1 << LOGV], const float* um, int qidx0) {
+__device__ __forceinline__ void xform_gen(T (&x)[1 << LOGV], T (&y)[1 << LOGV], cfptr um, int qidx0) {
   xform_gen_bit<0, LOGV, ADJ, ACTIVE>(x, y, um, qidx0);
 }
+
+// The input-side phase of general settings: element v gets prod_q e_q^(bit q of v), e_q the
+// phase of index bit q of an n-bit index, given by eq(q) as (re, im) (uniform); CONJ
+// multiplies by its conjugate (the adjoint, after the rotations).  Register i holds index
+// base | off(i), where off maps register bits to distinct index bits outside base's.  The
+// phase of base is a product over its set bits; the register part comes from two tables
+// (register bits 0..2 and 3..4) built by doubling, so no phase is more than six products deep.
+template <bool CONJ, int LOGV, typename T, typename Off, typename Eq>
+__device__ __forceinline__ void apply_gphase(T (&x)[1 << LOGV], T (&y)[1 << LOGV], uint32_t base, int n, Off off,
+                                             Eq eq) {
+  constexpr int V = 1 << LOGV;
+  constexpr int LA = LOGV < 3 ? LOGV : 3;  // register bits of the first table
+  constexpr int NA = 1 << LA, NB = V >> LA;
+  T br = T(1), bi = T(0);
+  for (int q = 0; q < n; ++q) {
+    const float2 e = eq(q);
+    const T nr = fma(br, (T)e.x, -bi * (T)e.y), ni = fma(br, (T)e.y, bi * (T)e.x);
+    const bool on = (base >> q) & 1u;
+    br = on ? nr : br;
+    bi = on ? ni : bi;
+  }
+  T ar[NA], ai[NA], hr[NB], hi[NB];
+  ar[0] = T(1);
+  ai[0] = T(0);
+  hr[0] = br;
+  hi[0] = bi;
+#pragma unroll
+  for (int k = 0; k < LOGV; ++k) {
+    const float2 e = eq(__builtin_ctz(off(1 << k)));
+    const T er = e.x, ei = e.y;
+    if (k < LA) {
+#pragma unroll
+      for (int i = 0; i < (1 << k); ++i) {
+        ar[i | (1 << k)] = fma(ar[i], er, -ai[i] * ei);
+        ai[i | (1 << k)] = fma(ar[i], ei, ai[i] * er);
+      }
+    } else {
+      const int kb = k - LA;
+#pragma unroll
+      for (int i = 0; i < (1 << kb); ++i) {
+        hr[i | (1 << kb)] = fma(hr[i], er, -hi[i] * ei);
+        hi[i | (1 << kb)] = fma(hr[i], ei, hi[i] * er);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int ia = i & (NA - 1), ib = i >> LA;
+    const T pr = fma(ar[ia], hr[ib], -ai[ia] * hi[ib]);
+    const T pi = CONJ ? -fma(ar[ia], hi[ib], ai[ia] * hr[ib]) : fma(ar[ia], hi[ib], ai[ia] * hr[ib]);
+    const T xr = x[i], xi = y[i];
+    x[i] = fma(xr, pr, -xi * pi);
+    y[i] = fma(xr, pi, xi * pr);
+  }
+}
+
+// Phase sources for apply_gphase: scalar loads of the setting's coefficients (any block
+// size), or a per-lane copy (lane q holds e_q; full wavefronts only) read out with
+// readlane, which keeps the loop over the index bits free of memory waits.
+struct PhaseLoad {
+  cfptr um;
+  __device__ float2 operator()(int q) const { return float2{uniform_f32(um[8 * q + 2]), uniform_f32(um[8 * q + 3])}; }
+};
+struct PhaseLanes {
+  float2 v;
+  __device__ float2 operator()(int q) const {
+    return float2{__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), q)),
+                  __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), q))};
+  }
+};
 
 // Orders the LDS accesses of a wavefront around an exchange between its lanes.
 // A wavefront's LDS operations execute in issue order; the fences keep the

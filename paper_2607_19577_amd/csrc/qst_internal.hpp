@@ -25,7 +25,7 @@ struct Geometry {
   int elem;      // bytes per real (4 or 8)
   int split_adj; // work-groups per adjoint tile at batch size S (partial-sum slices in the workspace)
   bool h16;      // the setting-batch intermediates X and W are stored in BF16
-  bool gen;      // general local settings: one 2x2 matrix per (setting, qubit) from the decode
+  bool gen;      // general local settings: a rotation and a phase per (setting, qubit) from the decode
   bool sparse;   // sparse (CSR) frequencies: chunk pointers in the workspace
 };
 
@@ -39,7 +39,7 @@ struct LoArgs {
   const void* grad_p;         // [B][D] or null (generic sensitivity)
   void* probs;                // [B][D] or null
   const void* pbase;          // [B][D] or null: base probabilities added to p
-  const float* um;            // general settings: [B][n][8] matrices by index bit (else null)
+  const float* um;            // general settings: [B][n][8] (tan(theta/2), sin(theta), Re e, Im e, 0...) by index bit (else null)
   // sparse frequencies (freqs then holds the non-zero values): fidx [nnz] outcomes, fchunk
   // [B * 2^n_hi + 1] the first non-zero of each (setting, high index) chunk; null: dense
   const int* fidx;
@@ -73,7 +73,7 @@ struct HiArgs {
   const void* src;  // forward: atoms [R][D];   adjoint: W [S][R][D]
   void* dst;        // forward: X [S][R][D];    adjoint: atom gradient [R][D]
   const uint64_t* pc;
-  const float* um;  // general settings: [B][n][8] matrices by index bit (else null)
+  const float* um;  // general settings: [B][n][8] (tan(theta/2), sin(theta), Re e, Im e, 0...) by index bit (else null)
   void* part;       // adjoint with nsplit > 1: per-split sums [nsplit][R][D]
   long long D;
   int R, n, n_lo, n_hi, t, c, b0, S, first;
@@ -138,9 +138,10 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
 // (rows from rowptr, outcomes in idx), cptr[B * nh] = nnz; every entry clamped to [0, nnz].
 hipError_t launch_chunk_ptr(const long long* rowptr, const int* idx, long long nnz, int B, int nh, int U,
                             long long* cptr, hipStream_t st);
-// General local settings: per (setting, qubit) the normalised 2x2 matrix (Pauli codes
-// 0..2 or unitaries[code - 3]) as 8 floats at um[(b * N + index bit) * 8]; pc gets code 0
-// for every qubit.  Codes >= 3 + K raise the flag and apply the identity.
+// General local settings: per (setting, qubit) the rotation form of its 2x2 (Pauli codes
+// 0..2 or unitaries[code - 3]), R = [[c, -s], [s, c]] after the input phase diag(1, e), as
+// (tan(theta/2), s, Re e, Im e) at um[(b * N + index bit) * 8]; pc gets code 0 for every qubit.  Codes
+// >= 3 + K raise flag bit 1, table entries that are not unitary raise bit 2 (both: identity).
 hipError_t launch_decode_general(const uint8_t* settings, int B, int N, const double* unitaries, int K, float* um,
                                  uint64_t* pc, int* flag, hipStream_t st);
 // part [rows][nslots] -> out[rows] (two-level, fixed order).  out_stride: spacing of out entries.

@@ -37,10 +37,15 @@ hipError_t launch_decode(const uint8_t* settings, int B, int N, uint64_t* pc, in
   return hipGetLastError();
 }
 
-// General local settings: thread (b, j) writes the normalised 2x2 matrix of qubit j
-// of setting b at um[(b N + N-1-j) 8 ..] (FP32; a00, a01, a10, a11 as re, im pairs):
-// the Pauli rotations for codes 0..2 (V_Z = I), unitaries[code - 3] (complex128)
-// beyond.  pc gets code 0 everywhere (every bit is applied).
+// General local settings: thread (b, j) writes the rotation form of qubit j of setting b
+// at um[(b N + N-1-j) 8 ..]: the matrix U (the Pauli rotations for codes 0..2, V_Z = I,
+// unitaries[code - 3] beyond) is P R diag(1, e) with P diagonal unitary, R = [[c, -s], [s, c]],
+// c = |u00|, s = |u10| and e = c u11' - s u01' (u' = the second column with P's phases
+// removed).  P multiplies each outcome's amplitude by a phase, which changes neither |phi|^2
+// nor V^dagger diag(g) V, so only (tan(theta/2) = s / (1 + c), s, Re e, Im e) are stored
+// (FP32, computed in FP64; theta in [0, pi/2] since c, s >= 0).
+// A table entry that is not unitary to 1e-6 raises flag bit 2 and acts as the identity;
+// codes beyond the table raise bit 1 (identity).  pc gets code 0 everywhere.
 __global__ void k_decode_general(const uint8_t* __restrict__ settings, int B, int N,
                                  const double* __restrict__ unitaries, int K, float* __restrict__ um,
                                  uint64_t* __restrict__ pc, int* __restrict__ flag) {
@@ -49,23 +54,47 @@ __global__ void k_decode_general(const uint8_t* __restrict__ settings, int B, in
   const int b = (int)(t / N);
   const int j = (int)(t - (long long)b * N);
   const uint32_t c = settings[t];
-  constexpr float r2 = 0.70710678118654752440f;
-  float m[8] = {1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
+  constexpr double r2 = 0.70710678118654752440;
+  // u00, u01, u10, u11 as (re, im)
+  double u[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
   if (c == 0u) {
-    const float v[8] = {r2, 0.f, r2, 0.f, r2, 0.f, -r2, 0.f};
-    for (int k = 0; k < 8; ++k) m[k] = v[k];
+    const double v[8] = {r2, 0.0, r2, 0.0, r2, 0.0, -r2, 0.0};
+    for (int k = 0; k < 8; ++k) u[k] = v[k];
   } else if (c == 1u) {
-    const float v[8] = {r2, 0.f, 0.f, -r2, r2, 0.f, 0.f, r2};
-    for (int k = 0; k < 8; ++k) m[k] = v[k];
+    const double v[8] = {r2, 0.0, 0.0, -r2, r2, 0.0, 0.0, r2};
+    for (int k = 0; k < 8; ++k) u[k] = v[k];
   } else if (c >= 3u) {
     if ((int)(c - 3u) < K) {
-      for (int k = 0; k < 8; ++k) m[k] = (float)unitaries[(size_t)(c - 3u) * 8 + k];
+      const double* m = unitaries + (size_t)(c - 3u) * 8;
+      for (int k = 0; k < 8; ++k) u[k] = m[k];
+      // U^dagger U = I: unit columns, orthogonal to each other
+      const double n0 = u[0] * u[0] + u[1] * u[1] + u[4] * u[4] + u[5] * u[5];
+      const double n1 = u[2] * u[2] + u[3] * u[3] + u[6] * u[6] + u[7] * u[7];
+      const double ore = u[0] * u[2] + u[1] * u[3] + u[4] * u[6] + u[5] * u[7];
+      const double oim = u[0] * u[3] - u[1] * u[2] + u[4] * u[7] - u[5] * u[6];
+      const bool ok = fabs(n0 - 1.0) <= 1e-6 && fabs(n1 - 1.0) <= 1e-6 && fabs(ore) <= 1e-6 && fabs(oim) <= 1e-6;
+      if (!ok) {
+        atomicOr(flag, 2);
+        const double id[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+        for (int k = 0; k < 8; ++k) u[k] = id[k];
+      }
     } else {
       atomicOr(flag, 1);
     }
   }
+  const double ca = hypot(u[0], u[1]), sa = hypot(u[4], u[5]);
+  // phases conj(u00)/|u00| and conj(u10)/|u10| (1 for a zero entry)
+  const double p0r = ca > 0.0 ? u[0] / ca : 1.0, p0i = ca > 0.0 ? -u[1] / ca : 0.0;
+  const double p1r = sa > 0.0 ? u[4] / sa : 1.0, p1i = sa > 0.0 ? -u[5] / sa : 0.0;
+  const double br = p0r * u[2] - p0i * u[3], bi = p0r * u[3] + p0i * u[2];  // u01'
+  const double dr = p1r * u[6] - p1i * u[7], di = p1r * u[7] + p1i * u[6];  // u11'
+  const double er = ca * dr - sa * br, ei = ca * di - sa * bi;
   float* dst = um + ((size_t)b * N + (N - 1 - j)) * 8;
-  for (int k = 0; k < 8; ++k) dst[k] = m[k];
+  dst[0] = (float)(sa / (1.0 + ca));
+  dst[1] = (float)sa;
+  dst[2] = (float)er;
+  dst[3] = (float)ei;
+  for (int k = 4; k < 8; ++k) dst[k] = 0.f;
   if (j == 0) pc[b] = 0ull;
 }
 

@@ -93,7 +93,7 @@ constexpr uint32_t chain_mask() {
 // matrices of the setting (um, by index bit) instead of the Pauli butterflies.
 template <int K, typename CH, bool WL, bool GEN, int LOGV, typename T>
 __device__ __forceinline__ void fwd_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc,
-                                          const float* um) {
+                                          cfptr um) {
   if constexpr (K < CH::count()) {
     if constexpr (K > 0) lo_transpose<WL, LOGV, CH::lo(K - 1), CH::lo(K)>(x, y, re, im, tau);
     if constexpr (GEN)
@@ -108,7 +108,7 @@ __device__ __forceinline__ void fwd_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], 
 // their own adjoints; the general ones take the conjugate transpose).
 template <int K, typename CH, bool WL, bool GEN, int LOGV, typename T>
 __device__ __forceinline__ void adj_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc,
-                                          const float* um) {
+                                          cfptr um) {
   if constexpr (GEN)
     xform_gen<LOGV, true, chain_mask<CH, K>()>(x, y, um, CH::lo(K));
   else
@@ -152,7 +152,8 @@ __device__ __forceinline__ void apply_phase(T (&x)[1 << LOGV], T (&y)[1 << LOGV]
 // PHASE: the state is one chunk (n = n_lo): the input is the atoms and this stage
 // applies the Y phases.  H16: the setting-batch intermediates X (input, when the state
 // has high bits) and W (output) are stored in BF16; arithmetic stays in T.  GEN:
-// general local settings (normalised 2x2 matrices per qubit, no phases, scale 1).
+// general local settings (a rotation per qubit, the input-side phase where the state
+// enters and leaves the rotations, scale 1).
 template <typename T, int N_LO, bool ADJ, bool PHASE, bool H16, bool GEN = false>
 __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
   using C2 = cx<T>;
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
     const T al = active ? (T)a.alpha[atom] : T(0);
     const uint64_t pc = uniform_u64(a.pc[b]);
     const T s2 = GEN ? T(1) : (T)ldexp(1.0, -nonz_count(pc, a.n));
-    const float* um = GEN ? a.um + (size_t)b * a.n * 8 : nullptr;
+    const cfptr um = GEN ? to_const(a.um + (size_t)b * a.n * 8) : nullptr;
     const double Bd = (double)a.B;
     const float inv_b = (float)(1.0 / Bd);
     const float eps_f = (float)a.eps;
@@ -300,6 +301,8 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
       ym = ymask_of(pc, a.n);
       apply_phase<false, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
     }
+    if constexpr (PHASE && GEN)
+      apply_gphase<false, LOGV>(x, y, pos0, a.n, [](int i) { return (uint32_t)(i << LO0); }, PhaseLoad{um});
     fwd_chain<0, CH, WL, GEN, LOGV>(x, y, re, im, tau, pc, um);
     // Final layout is lo = 0: alpha_r |phi_r|^2 into LDS, reduced over atoms per outcome.
     T* qrow = qb + (size_t)atom * UPAD + pad_base<LOGV, 0>(tau);
@@ -412,6 +415,8 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
       if constexpr (!WL) __syncthreads();  // every thread has read g before the planes are reused
       adj_chain<NL - 1, CH, WL, GEN, LOGV>(x, y, re, im, tau, pc, um);
       if constexpr (PHASE && !GEN) apply_phase<true, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
+      if constexpr (PHASE && GEN)
+        apply_gphase<true, LOGV>(x, y, pos0, a.n, [](int i) { return (uint32_t)(i << LO0); }, PhaseLoad{um});
       unsigned char* dbase = reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + ((long long)h << N_LO)) * CBO;
       const rsrc_t rd = make_rsrc(dbase, extent(a, CBO));
       const uint32_t vo0 = voff(a, CBO);
@@ -490,7 +495,8 @@ constexpr uint32_t rows_mask(int lo, int c, int top) {
 }
 
 // H16: X (forward output) and W (adjoint input) are stored in BF16.  GEN: general
-// local settings (the setting's 2x2 matrices of the high bits, no phases).
+// local settings (the input-side phase of every bit, then the rotations of the high bits;
+// the adjoint in reverse order).
 template <int TB, int N_HI, bool ADJ, bool H16, bool GEN = false>
 __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   using T = float;
@@ -532,12 +538,25 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   auto off0 = [=](int i) { return tile_off((uint32_t)i << LO0, C, n_lo); };
   auto offf = [=](int i) { return tile_off((uint32_t)i << LOF, C, n_lo); };
 
+  // General settings: lane q of every wavefront holds the phase e_q of the setting
+  // (fetched one setting ahead) for the per-element phase.
+  const int lane = tid & 63;
+  auto lane_e = [&](int s) -> float2 {
+    float2 e{0.f, 0.f};
+    if (lane < a.n) e = *reinterpret_cast<const float2*>(a.um + ((size_t)(a.b0 + s) * a.n + lane) * 8 + 2);
+    return e;
+  };
+
   if (!ADJ) {
     const rsrc_t rs = make_rsrc(reinterpret_cast<const C2*>(a.src) + origin, vbytes);
     T kx[V], ky[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       bload2(kx[i], ky[i], rs, vo0, off0(i) * CB);
+    }
+    float2 ecur{0.f, 0.f};
+    if constexpr (GEN) {
+      if (s_lo < s_hi) ecur = lane_e(s_lo);
     }
     for (int s = s_lo; s < s_hi; ++s) {
       const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
@@ -548,8 +567,12 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         y[i] = ky[i];
       }
       if constexpr (GEN) {
+        float2 enxt = ecur;
+        if (s + 1 < s_hi) enxt = lane_e(s + 1);
         // register bit k of layout lo is index bit n_lo + lo + k - C
-        const float* um = a.um + (size_t)(a.b0 + s) * a.n * 8;
+        const cfptr um = to_const(a.um + (size_t)(a.b0 + s) * a.n * 8);
+        apply_gphase<false, LOGV>(x, y, cbase | t0, a.n, off0, PhaseLanes{ecur});
+        ecur = enxt;
         xform_gen<LOGV, false, M0>(x, y, um, n_lo + LO0 - C);
         if constexpr (TWO) {
           lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
@@ -575,22 +598,25 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
     // Two register buffers take turns: the next setting's W tile is fetched into one
     // while the other is transformed in place.
     T px[V], py[V], qx[V], qy[V];
-    auto issue = [&](int s, T (&bx)[V], T (&by)[V]) __attribute__((always_inline)) {
+    float2 pe{0.f, 0.f}, qe{0.f, 0.f};
+    auto issue = [&](int s, T (&bx)[V], T (&by)[V], float2& be) __attribute__((always_inline)) {
       const rsrc_t rw = make_rsrc(
           reinterpret_cast<const unsigned char*>(a.src) + ((long long)s * a.R * D + origin) * CBH, vbytes_h);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         ld_cs<H16>(bx[i], by[i], rw, t0 * CBH, off0(i) * CBH);
       }
+      if constexpr (GEN) be = lane_e(s);
     };
-    auto body = [&](int s, T (&x)[V], T (&y)[V]) __attribute__((always_inline)) {
+    auto body = [&](int s, T (&x)[V], T (&y)[V], const float2& e) __attribute__((always_inline)) {
       if constexpr (GEN) {
-        const float* um = a.um + (size_t)(a.b0 + s) * a.n * 8;
+        const cfptr um = to_const(a.um + (size_t)(a.b0 + s) * a.n * 8);
         xform_gen<LOGV, true, M0>(x, y, um, n_lo + LO0 - C);
         if constexpr (TWO) {
           lds_transpose<LOGV, LO0, LO1>(x, y, re, im, tid);
           xform_gen<LOGV, true, M1>(x, y, um, n_lo + LO1 - C);
         }
+        apply_gphase<true, LOGV>(x, y, cbase | tf, a.n, offf, PhaseLanes{e});
       } else {
         const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
         const uint32_t ym = ymask_of(pc, a.n);
@@ -607,13 +633,13 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         ay[i] += y[i];
       }
     };
-    if (s_lo < s_hi) issue(s_lo, px, py);
+    if (s_lo < s_hi) issue(s_lo, px, py, pe);
     for (int s = s_lo; s < s_hi; s += 2) {
-      if (s + 1 < s_hi) issue(s + 1, qx, qy);
-      body(s, px, py);
+      if (s + 1 < s_hi) issue(s + 1, qx, qy, qe);
+      body(s, px, py, pe);
       if (s + 1 < s_hi) {
-        if (s + 2 < s_hi) issue(s + 2, px, py);
-        body(s + 1, qx, qy);
+        if (s + 2 < s_hi) issue(s + 2, px, py, pe);
+        body(s + 1, qx, qy, qe);
       }
     }
     // one split: accumulate into the gradient; several: this split's sum to its slice

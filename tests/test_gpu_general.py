@@ -122,6 +122,26 @@ def test_code_beyond_the_table_raises_the_flag(h):
     api.qst_forward(h, [_inst(_case(1671, 6, 2, 4))], want_probs=True)  # the flag was cleared
 
 
+def test_non_unitary_table_entry_raises_the_flag(h):
+    """The kernels apply each table entry in rotation form, which needs a unitary: an entry off
+    unitarity by more than 1e-6 is flagged (and acts as the identity); the flag is then cleared."""
+    from paper_2607_19577_amd import api
+
+    c = _case(1672, 6, 2, 4, K=2)
+    c["settings"][2, 1] = 3 + 1
+    bad = c["table"].copy()
+    bad[1] *= 1.001  # columns no longer of unit norm
+    inst = api.Instance(torch.from_numpy(c["atoms"]).to(DEV), torch.from_numpy(c["weights"]).to(DEV),
+                        torch.from_numpy(c["settings"]).to(DEV), torch.from_numpy(c["freqs"]).to(DEV),
+                        unitaries=torch.from_numpy(bad).to(DEV))
+    api.qst_forward(h, [inst], want_probs=True)
+    torch.cuda.synchronize()
+    with pytest.raises(api.QSTError, match="not unitary"):
+        api.qst_forward(h, [_inst(c)], want_probs=True)
+    torch.cuda.synchronize()
+    api.qst_forward(h, [_inst(c)], want_probs=True)  # the flag was cleared
+
+
 def test_autograd_with_general_settings_and_sparse_data(h):
     """torch.autograd through the general-settings forward (caller's dL/dp) and the fused loss on
     sparse frequencies, against the oracle's gradients (torch's complex gradient is twice the
