@@ -424,6 +424,22 @@ def main():
         fwd_ms = med3(lambda: api.qst_forward(h, [inst], want_probs=True, loss=api.LOSS_CE, eps=1e-8))
         trial_ms = med3(lambda: api.qst_atom_trial(h, inst, R // 2, trial, p_t[0], loss=api.LOSS_CE, eps=1e-8))
         del p_t
+        # the unfused autograd route: probabilities through the forward map, the loss in torch,
+        # the caller's dL/dp through the adjoint (generic-sensitivity mode)
+        from paper_2607_19577_amd.autograd import born_map
+
+        a_req = inst.atoms.detach().clone().requires_grad_(True)
+        w_req = inst.weights.detach().clone().requires_grad_(True)
+
+        def autograd_route():
+            p = born_map(a_req, w_req, inst.settings, h)
+            loss = -((freqs / B) * torch.log(p / B + 1e-8)).sum()
+            loss.backward()
+            a_req.grad = None
+            w_req.grad = None
+
+        extras["autograd_route_ms"] = round(med3(autograd_route), 1)
+        del a_req, w_req
         extras["forward_probs_loss_ms"] = round(fwd_ms, 1)
         extras["atom_trial_ms"] = round(trial_ms, 1)
         extras["atom_trial_speedup_vs_forward"] = round(fwd_ms / trial_ms, 2)
