@@ -27,7 +27,7 @@ struct qst_handle {
   void* ws = nullptr;  // workspace arena (grow-only)
   size_t ws_bytes = 0;
   std::vector<void*> retired;  // outgrown arenas, freed by qst_destroy (captured graphs may still use them)
-  int* dflag = nullptr;  // device flag raised by kernels (bad Pauli code)
+  int* dflag = nullptr;  // device flag raised by kernels (OR of 1: bad code, 2: table entry not unitary)
   int* hflag = nullptr;  // pinned host copy
   hipEvent_t flag_ev = nullptr;
   bool flag_pending = false;

@@ -141,7 +141,7 @@ hipError_t launch_chunk_ptr(const long long* rowptr, const int* idx, long long n
 // General local settings: per (setting, qubit) the rotation form of its 2x2 (Pauli codes
 // 0..2 or unitaries[code - 3]), R = [[c, -s], [s, c]] after the input phase diag(1, e), as
 // (tan(theta/2), s, Re e, Im e) at um[(b * N + index bit) * 8]; pc gets code 0 for every qubit.  Codes
-// >= 3 + K raise flag bit 1, table entries that are not unitary raise bit 2 (both: identity).
+// >= 3 + K OR 1 into the flag, table entries that are not unitary OR in 2 (both: identity).
 hipError_t launch_decode_general(const uint8_t* settings, int B, int N, const double* unitaries, int K, float* um,
                                  uint64_t* pc, int* flag, hipStream_t st);
 // part [rows][nslots] -> out[rows] (two-level, fixed order).  out_stride: spacing of out entries.

@@ -44,8 +44,8 @@ hipError_t launch_decode(const uint8_t* settings, int B, int N, uint64_t* pc, in
 // removed).  P multiplies each outcome's amplitude by a phase, which changes neither |phi|^2
 // nor V^dagger diag(g) V, so only (tan(theta/2) = s / (1 + c), s, Re e, Im e) are stored
 // (FP32, computed in FP64; theta in [0, pi/2] since c, s >= 0).
-// A table entry that is not unitary to 1e-6 raises flag bit 2 and acts as the identity;
-// codes beyond the table raise bit 1 (identity).  pc gets code 0 everywhere.
+// A table entry that is not unitary to 1e-6 ORs 2 into the flag and acts as the identity;
+// codes beyond the table OR in 1 (identity).  pc gets code 0 everywhere.
 __global__ void k_decode_general(const uint8_t* __restrict__ settings, int B, int N,
                                  const double* __restrict__ unitaries, int K, float* __restrict__ um,
                                  uint64_t* __restrict__ pc, int* __restrict__ flag) {

@@ -453,12 +453,18 @@ hipError_t launch_lo_n(const Geometry& g, const LoBatch& m, bool adjoint, hipStr
   const size_t lds = lo_lds_bytes(g);
   const unsigned grid = (unsigned)g.grid_lo;
   if (adjoint) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16, GEN>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16, GEN>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
     k_stage_lo<T, N_LO, true, PHASE, H16, GEN><<<grid, nthr, lds, st>>>(m);
   } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, false, PHASE, H16, GEN>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, false, PHASE, H16, GEN>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
     k_stage_lo<T, N_LO, false, PHASE, H16, GEN><<<grid, nthr, lds, st>>>(m);
   }
   return hipGetLastError();
@@ -469,8 +475,9 @@ int lo_occupancy_n(const Geometry& g) {
   constexpr int LOGV = N_LO < 5 ? N_LO : 5;
   const int nthr = g.R << (N_LO - LOGV);
   const size_t lds = lo_lds_bytes(g);
-  hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16, GEN>),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16, GEN>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 1;
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_stage_lo<T, N_LO, true, PHASE, H16, GEN>, nthr, lds) !=
       hipSuccess)
@@ -666,12 +673,18 @@ hipError_t launch_hi_n(const Geometry& g, const HiArgs& a, bool adjoint, hipStre
   const size_t lds = hi_lds_bytes(g);
   const unsigned grid = (unsigned)((g.R << (g.n_lo - g.c)) * a.nsplit);
   if (adjoint) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, true, H16, GEN>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, true, H16, GEN>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
     k_stage_hi<TB, N_HI, true, H16, GEN><<<grid, nthr, lds, st>>>(a);
   } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, false, H16, GEN>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_hi<TB, N_HI, false, H16, GEN>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
     k_stage_hi<TB, N_HI, false, H16, GEN><<<grid, nthr, lds, st>>>(a);
   }
   return hipGetLastError();
