@@ -272,7 +272,7 @@ def main():
 
     cpu = cpu_ref = None
     if not args.no_cpu_baseline:
-        n_sample = 2 if n >= 18 else min(B, 64 if n <= 12 else 8)
+        n_sample = 16 if n >= 18 else min(B, 64 if n <= 12 else 8)
         cpu, cpu_ref = cpu_baseline(atoms, w, s, B, shots, n_sample, seed + 7)
         print(f"[bench] cpu baseline: {cpu['value']:.3e} amplitudes/s ({cpu['sample']})", file=sys.stderr, flush=True)
 
