@@ -265,3 +265,33 @@ def test_full_size_gradient_on_setting_subset(h, big):
     # the MFMA tile paths on the same sampled settings (tolerance of the FP16/BF16 variants)
     for path in (api.PATH_TILE_F16, api.PATH_TILE_BF16):
         _check(_run(h, case, api.LOSS_CE, path), ref, 1e-2, f"n=20 subset tile path {path}")
+
+
+# ---------------------------------------------------------------- n = 20 at the smallest ranks
+@pytest.mark.parametrize("n,R", [(20, 1), (20, 2)])
+def test_smallest_ranks_at_n20_sampled_rows_and_closed_forms(h, n, R):
+    """The largest low stages (n_lo = 14 and 13, six and seven high bits; the spectral step's G v
+    runs at R = 1): one setting's probabilities against the oracle, and the adjoint's closed form
+    g = 1 -> alpha_r B psi_r, B ||psi_r||^2."""
+    from paper_2607_19577_amd import api
+
+    B = 3
+    rng = synth.make_rng(7100 + n)
+    atoms = synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64)
+    w = synth.dirichlet_weights(rng, R)
+    s = synth.random_settings(rng, B, n)
+    inst = api.Instance(torch.from_numpy(atoms).to(DEV), torch.from_numpy(w).to(DEV), torch.from_numpy(s).to(DEV))
+    probs, _ = api.qst_forward(h, [inst], want_probs=True)
+    torch.cuda.synchronize()
+    psi = atoms.astype(np.complex128)
+    ref = born.probs_axis(psi, w, s, rows=[1])[0]
+    got = probs[0][1].cpu().numpy()
+    assert close(got, ref, TOL32), rel(got, ref)
+    del probs
+    ones = torch.ones((B, 1 << n), dtype=torch.float32, device=DEV)
+    _, ag, wg = api.qst_backward(h, [inst], grad_p=[ones])
+    torch.cuda.synchronize()
+    g = ag[0].cpu().numpy()
+    for r in range(R):
+        assert close(g[r], w[r] * B * psi[r], TOL32), (r, rel(g[r], w[r] * B * psi[r]))
+    assert close(wg[0].cpu().numpy(), B * (np.abs(psi) ** 2).sum(axis=1), TOL32)
