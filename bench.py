@@ -166,12 +166,24 @@ def solve_extra(api, h, dev, seed: int, slots: int = 100):
     dt = time.perf_counter() - t0
     e1 = api.qst_state_error(h, res["atoms"].contiguous(), res["weights"].contiguous(), truth, wt)
     hist = res["history"]
-    return {"workload": "n=14, R_max=8, B=1000, 1e5 shots, truth rank 4; t_alpha=5, t_ref=10, grid 2^-j (11)",
-            "slots": res["slots"], "stopped": res["stopped"], "wall_s": round(dt, 2),
-            "ms_per_slot": round(dt * 1e3 / max(res["slots"], 1), 2), "accepted": int(hist[:, 4].sum()),
-            "oracle_calls": res["oracle_calls"], "rank_final": res["rank"],
-            "J_first_slot": round(float(hist[0, 2]), 6), "J_final": round(float(hist[-1, 2]), 6),
-            "e_rho_initial": round(e0, 4), "e_rho_final": round(e1, 4)}
+    out = {"workload": "n=14, R_max=8, B=1000, 1e5 shots, truth rank 4; t_alpha=5, t_ref=10, grid 2^-j (11)",
+           "slots": res["slots"], "stopped": res["stopped"], "wall_s": round(dt, 2),
+           "ms_per_slot": round(dt * 1e3 / max(res["slots"], 1), 2), "accepted": int(hist[:, 4].sum()),
+           "oracle_calls": res["oracle_calls"], "rank_final": res["rank"],
+           "J_first_slot": round(float(hist[0, 2]), 6), "J_final": round(float(hist[-1, 2]), 6),
+           "e_rho_initial": round(e0, 4), "e_rho_final": round(e1, 4)}
+    # Which moves are enabled (ablation section): atom steps only, atom and coefficient steps, and
+    # the full schedule, from the same start, each for the same number of slots (no early stop).
+    abl = {}
+    for name, ta, tr in (("atom_only", 0, 0), ("atom_coeff", 5, 0), ("full", 5, 10)):
+        pv = api.SolveParams(max_slots=slots, t_alpha=ta, t_ref=tr, rank_max=Rmax, n_lanczos=30, stop_window=0)
+        rv = api.qst_solve(h, api.Instance(atoms0, w0, s, f), pv, v0s)
+        ev = api.qst_state_error(h, rv["atoms"].contiguous(), rv["weights"].contiguous(), truth, wt)
+        abl[name] = {"slots": rv["slots"], "accepted": int(rv["history"][:, 4].sum()),
+                     "oracle_calls": rv["oracle_calls"], "rank_final": rv["rank"],
+                     "J_final": round(float(rv["history"][-1, 2]), 6), "e_rho_final": round(ev, 4)}
+    out["ablation"] = abl
+    return out
 
 
 def uneven_batch_extra(api, h, dev, seed: int, reps: int = 5):
