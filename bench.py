@@ -364,6 +364,13 @@ def main():
                 "traffic": traffic, "kernel": names[dom], "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": per_launch_bytes[dom]}
     model_bytes_step = sum((per_launch_bytes[k] or 0) * stages[k][0] for k in per_launch_bytes) / args.steps
+    # every stage against the same peak: algorithmic bytes per launch / average launch time
+    stage_bw = {}
+    for k, b in per_launch_bytes.items():
+        nk, tk = stages[k]
+        if b and nk and tk > 0:
+            gbps = b / (tk / nk * 1e-3) / 1e9
+            stage_bw[names[k]] = {"GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)}
 
     extras = {}
     if cpu_ref is not None:
@@ -488,6 +495,7 @@ def main():
                            "iqr": round(float(np.percentile(step_ms, 75) - np.percentile(step_ms, 25)), 3),
                            "min": round(float(step_ms.min()), 3), "max": round(float(step_ms.max()), 3)},
         "stage_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in stages.items()},
+        "stage_bandwidth": stage_bw,
         "model_hbm_bytes_per_step": model_bytes_step,
         "model_GBps_whole_step": round(model_bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
         "kernel_source_hash": kernel_source_hash(),
