@@ -379,16 +379,29 @@ def main():
         ns = cpu_ref["freqs"].shape[0]
         sub = api.Instance(inst.atoms, inst.weights, inst.settings[:ns].contiguous(),
                            torch.from_numpy(cpu_ref["freqs"]).to(dev))
-        lt_s, ag_s, wg_s = api.qst_backward(h, [sub], loss=api.LOSS_CE, eps=1e-8, path=step_path)
-        torch.cuda.synchronize()
+        def path_errors(pth):
+            lt_s, ag_s, wg_s = api.qst_backward(h, [sub], loss=api.LOSS_CE, eps=1e-8, path=pth)
+            torch.cuda.synchronize()
+            return {"loss": _relerr(float(lt_s[0]), cpu_ref["loss"]),
+                    "weight_grad": _relerr(wg_s[0].cpu().numpy(), cpu_ref["weight_grad"]),
+                    "atom_grad": _relerr(ag_s[0].cpu().numpy(), cpu_ref["atom_grad"])}
+
         tol = 1e-5 if args.path == "butterfly_f32" else 1e-2
-        errs = {"loss": _relerr(float(lt_s[0]), cpu_ref["loss"]),
-                "weight_grad": _relerr(wg_s[0].cpu().numpy(), cpu_ref["weight_grad"]),
-                "atom_grad": _relerr(ag_s[0].cpu().numpy(), cpu_ref["atom_grad"])}
+        errs = path_errors(step_path)
         extras["errors_vs_oracle"] = {"settings": ns, "norm": "||x - x_oracle|| / ||x_oracle||",
                                       **{k: float(f"{v:.3e}") for k, v in errs.items()}, "tol": tol,
                                       "pass": all(v <= tol for v in errs.values())}
-        del sub, lt_s, ag_s, wg_s, cpu_ref
+        if not args.no_extras:
+            # the other paths on the same sample, beside their timings below
+            other = {}
+            for name, pth, ptol in (("plain_f32", api.PATH_PLAIN_F32, 1e-5), ("tile_f16", api.PATH_TILE_F16, 1e-2),
+                                    ("tile_bf16", api.PATH_TILE_BF16, 1e-2),
+                                    ("butterfly_bf16", api.PATH_BUTTERFLY_BF16, 1e-2)):
+                e = path_errors(pth)
+                other[name] = {**{k: float(f"{v:.3e}") for k, v in e.items()}, "tol": ptol,
+                               "pass": all(v <= ptol for v in e.values())}
+            extras["errors_vs_oracle_other_paths"] = other
+        del sub, cpu_ref
     if not args.no_extras:
         # plain one-pass-per-qubit reference kernel on the same workload (one call)
         torch.cuda.synchronize()
