@@ -154,10 +154,23 @@ __device__ __forceinline__ void apply_phase(T (&x)[1 << LOGV], T (&y)[1 << LOGV]
 // has high bits) and W (output) are stored in BF16; arithmetic stays in T.  GEN:
 // general local settings (a rotation per qubit, the input-side phase where the state
 // enters and leaves the rotations, scale 1).
+// Register bits per thread of the low stage: 2^5 values, or 2^4 in the forward pass over
+// staged chunks of 2^12 and more outcomes (ranks up to 4), which then runs up to 1024
+// threads per work-group: twice the wavefronts to overlap its loads and barriers.  (The
+// adjoint pass keeps 2^5: with 1024 threads its registers would spill.)
+template <int N_LO, bool PHASE, bool ADJ>
+constexpr int lo_logv() {
+  return N_LO < 5 ? N_LO : ((N_LO >= 12 && !PHASE && !ADJ) ? 4 : 5);
+}
+template <int N_LO, bool PHASE, bool ADJ>
+constexpr int lo_max_threads() {
+  return lo_logv<N_LO, PHASE, ADJ>() == 4 ? 1024 : 512;
+}
+
 template <typename T, int N_LO, bool ADJ, bool PHASE, bool H16, bool GEN = false>
-__global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
+__global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_lo(const LoBatch m) {
   using C2 = cx<T>;
-  constexpr int LOGV = N_LO < 5 ? N_LO : 5;
+  constexpr int LOGV = lo_logv<N_LO, PHASE, ADJ>();
   constexpr int V = 1 << LOGV;
   constexpr int U = 1 << N_LO;
   constexpr int UPAD = U + (U >> 5);
@@ -448,8 +461,7 @@ __global__ __launch_bounds__(512) void k_stage_lo(const LoBatch m) {
 
 template <typename T, int N_LO, bool PHASE, bool H16, bool GEN = false>
 hipError_t launch_lo_n(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
-  constexpr int LOGV = N_LO < 5 ? N_LO : 5;
-  const int nthr = m.rmax << (N_LO - LOGV);
+  const int nthr = m.rmax << (N_LO - (adjoint ? lo_logv<N_LO, PHASE, true>() : lo_logv<N_LO, PHASE, false>()));
   const size_t lds = lo_lds_bytes(g);
   const unsigned grid = (unsigned)g.grid_lo;
   if (adjoint) {
@@ -472,7 +484,7 @@ hipError_t launch_lo_n(const Geometry& g, const LoBatch& m, bool adjoint, hipStr
 
 template <typename T, int N_LO, bool PHASE, bool H16, bool GEN = false>
 int lo_occupancy_n(const Geometry& g) {
-  constexpr int LOGV = N_LO < 5 ? N_LO : 5;
+  constexpr int LOGV = lo_logv<N_LO, PHASE, true>();
   const int nthr = g.R << (N_LO - LOGV);
   const size_t lds = lo_lds_bytes(g);
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16, GEN>),
