@@ -156,19 +156,17 @@ qst_status make_geometry(qst_handle* h, int n, int R, int B, qst_path path, Geom
   const long long cap = elem == 4 ? 16384 : 8192;  // amplitudes one low-stage work-group holds
   constexpr size_t kLdsMax = 160 * 1024;
   int n_lo = n;
-  // registers per thread of the low stage: 2^4 in the forward pass over staged chunks of 2^12
-  // and more outcomes (the adjoint keeps 2^5; the workspace is sized for the larger thread count)
-  auto logv_of = [&](int nl) { return (nl >= 12 && nl < n) ? 4 : std::min(5, nl); };
   for (; n_lo > 0; --n_lo) {
     if (((long long)R << n_lo) > cap) continue;
     g.n_lo = n_lo;
-    g.logv_lo = logv_of(n_lo);
-    if (qst::lo_lds_bytes(g) <= kLdsMax) break;
+    g.n_hi = n - n_lo;
+    g.logv_lo = qst::lo_logv_of(n_lo, n_lo < n, true);
+    if (qst::lo_lds_bytes(g) <= kLdsMax) break;  // the larger of the forward and the adjoint pass
   }
   if (n_lo < 1) return set_err(h, QST_ERR_SHAPE, "rank too large for the on-chip low stage");
   g.n_lo = n_lo;
   g.n_hi = n - n_lo;
-  g.logv_lo = logv_of(n_lo);
+  g.logv_lo = qst::lo_logv_of(n_lo, n_lo < n, true);
   if (g.n_hi > 0) {
     if (elem != 4)
       return set_err(h, QST_ERR_UNSUPPORTED,

@@ -188,6 +188,14 @@ hipError_t launch_convert(const void* src, int src_c64, void* dst, int dst_c64, 
                           hipStream_t st);
 hipError_t launch_axpy_c(void* y, int y_c64, const void* x, int x_c64, long long n, double a, hipStream_t st);
 
+// Register bits per thread of the low stage (2^logv values): 5, or 4 in the forward pass
+// over staged chunks of 2^12 and more outcomes (ranks up to 4: twice the wavefronts).
+constexpr int lo_logv_of(int n_lo, bool staged, bool adjoint) {
+  return n_lo < 5 ? n_lo : ((staged && !adjoint && n_lo >= 12) ? 4 : 5);
+}
+// LDS of the low stage with 2^logv values per thread; lo_lds_bytes: the larger of the
+// forward and the adjoint pass.
+size_t lo_lds_bytes_logv(const Geometry& g, int logv);
 size_t lo_lds_bytes(const Geometry& g);
 int lo_blocks_per_cu(const Geometry& g);
 size_t hi_lds_bytes(const Geometry& g);

@@ -166,17 +166,24 @@ hipError_t launch_fill(void* p, size_t bytes, hipStream_t st) {
 // Low-stage LDS: the transpose planes, the |phi|^2 table [R][Upad] and the
 // sensitivity row [Upad] (layouts below), then one double per thread for the
 // reductions.
-size_t lo_lds_bytes(const Geometry& g) {
+size_t lo_lds_bytes_logv(const Geometry& g, int logv) {
   const size_t U = (size_t)1 << g.n_lo;
   const size_t Upad = U + (U >> 5);
-  const size_t nthr = (size_t)g.R << (g.n_lo - g.logv_lo);
+  const size_t nthr = (size_t)g.R << (g.n_lo - logv);
   // Wavefront-local transposes (at most 64 threads per atom): one plane per atom
   // plus a separate |phi|^2 table and g row; otherwise two planes per atom that
   // the table and the g row alias.
-  const bool wave_local = g.n_lo - g.logv_lo <= 6;
+  const bool wave_local = g.n_lo - logv <= 6;
   const size_t rows = wave_local ? 2 * (size_t)g.R + 1 : 2 * (size_t)g.R;
   const size_t planes = ((rows * Upad * g.elem) + 15) & ~(size_t)15;
   return planes + nthr * sizeof(double);
+}
+
+size_t lo_lds_bytes(const Geometry& g) {
+  const bool staged = g.n_hi > 0;
+  const size_t f = lo_lds_bytes_logv(g, lo_logv_of(g.n_lo, staged, false));
+  const size_t b = lo_lds_bytes_logv(g, lo_logv_of(g.n_lo, staged, true));
+  return f > b ? f : b;
 }
 
 // ------------------------------------------------------------------ stage dispatch

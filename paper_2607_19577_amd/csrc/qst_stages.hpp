@@ -154,13 +154,13 @@ __device__ __forceinline__ void apply_phase(T (&x)[1 << LOGV], T (&y)[1 << LOGV]
 // has high bits) and W (output) are stored in BF16; arithmetic stays in T.  GEN:
 // general local settings (a rotation per qubit, the input-side phase where the state
 // enters and leaves the rotations, scale 1).
-// Register bits per thread of the low stage: 2^5 values, or 2^4 in the forward pass over
-// staged chunks of 2^12 and more outcomes (ranks up to 4), which then runs up to 1024
-// threads per work-group: twice the wavefronts to overlap its loads and barriers.  (The
-// adjoint pass keeps 2^5: with 1024 threads its registers would spill.)
+// Register bits per thread of the low stage (lo_logv_of): the forward pass over staged
+// chunks of 2^12 and more outcomes takes 2^4 values per thread and up to 1024 threads per
+// work-group, twice the wavefronts to overlap its loads and barriers.  The adjoint keeps
+// 2^5 values: with 1024 threads its registers would spill.
 template <int N_LO, bool PHASE, bool ADJ>
 constexpr int lo_logv() {
-  return N_LO < 5 ? N_LO : ((N_LO >= 12 && !PHASE && !ADJ) ? 4 : 5);
+  return lo_logv_of(N_LO, !PHASE, ADJ);
 }
 template <int N_LO, bool PHASE, bool ADJ>
 constexpr int lo_max_threads() {
@@ -461,8 +461,9 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
 
 template <typename T, int N_LO, bool PHASE, bool H16, bool GEN = false>
 hipError_t launch_lo_n(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
-  const int nthr = m.rmax << (N_LO - (adjoint ? lo_logv<N_LO, PHASE, true>() : lo_logv<N_LO, PHASE, false>()));
-  const size_t lds = lo_lds_bytes(g);
+  const int logv = adjoint ? lo_logv<N_LO, PHASE, true>() : lo_logv<N_LO, PHASE, false>();
+  const int nthr = m.rmax << (N_LO - logv);
+  const size_t lds = lo_lds_bytes_logv(g, logv);
   const unsigned grid = (unsigned)g.grid_lo;
   if (adjoint) {
     {
@@ -486,7 +487,7 @@ template <typename T, int N_LO, bool PHASE, bool H16, bool GEN = false>
 int lo_occupancy_n(const Geometry& g) {
   constexpr int LOGV = lo_logv<N_LO, PHASE, true>();
   const int nthr = g.R << (N_LO - LOGV);
-  const size_t lds = lo_lds_bytes(g);
+  const size_t lds = lo_lds_bytes_logv(g, LOGV);
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_stage_lo<T, N_LO, true, PHASE, H16, GEN>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 1;
