@@ -231,7 +231,7 @@ int default_S(const Geometry& g) {
   if (s > g.B) s = g.B;
   // X and W hold S settings each (8 GiB each at most, S = 64 at n=20, R=16).  Larger
   // batches amortise the psi read and the gradient update and need fewer launches
-  // (measured at n=20, R=16, B=2000: S = 16 -> 267, 32 -> 251, 64 -> 243 ms per step).
+  // (measured at n=20, R=16, B=2000: S = 4 -> 337, 16 -> 253, 64 -> 229 ms per step).
   return (int)s;
 }
 
