@@ -256,6 +256,8 @@ def main():
                          "BF16 intermediates (1e-2 variant)")
     ap.add_argument("--batch", type=int, default=0, help="settings per batch (0: library default or --autotune)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only a 1 GiB device copy (counter scale)")
+    ap.add_argument("--only", choices=["uneven64", "solve"], default=None,
+                    help="run only one extra (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -264,6 +266,21 @@ def main():
     n, R, B, shots = wl["n"], wl["R"], wl["B"], wl["shots"]
     D = 1 << n
     seed = 20260101
+
+    if args.only:
+        import torch
+
+        from paper_2607_19577_amd import api
+
+        dev = torch.device("cuda:0")
+        h = api.Handle(0)
+        if args.only == "uneven64":
+            res = uneven_batch_extra(api, h, dev, seed + 21)
+        else:
+            res = solve_extra(api, h, dev, seed + 31)
+        print(json.dumps({args.only: res}), flush=True)
+        h.close()
+        return
 
     if args.copy_calibration:
         import torch
