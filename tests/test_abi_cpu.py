@@ -115,3 +115,63 @@ def test_create_without_device(lib):
     rc = lib.qst_create(4096, None, ctypes.byref(h))
     assert rc in (1, 5) and not h.value
     assert lib.qst_destroy(None) == 1
+
+
+def test_validation_of_general_sparse_trial_and_iteration(lib):
+    """Argument checks of the later entry points and instance fields (validation-only handle:
+    valid arguments come back as QST_ERR_UNSUPPORTED = 4 before any launch)."""
+    h = _vh(lib)
+    try:
+        def fwd(inst, path=0):
+            arr = (_lib.QstInstance * 1)(inst)
+            return lib.qst_forward(h, arr, 1, None, None, _lib.LOSS_NONE, 0.0, path)
+
+        # general local settings: table size, alignment, path
+        for k, addr, want in ((3, 0x5000, 4), (0, 0x5000, 2), (254, 0x5000, 2), (3, 0x5004, 3)):
+            g = _inst()
+            g.unitaries, g.n_unitaries = addr, k
+            assert fwd(g) == want, (k, addr)
+        g = _inst()
+        g.unitaries, g.n_unitaries = 0x5000, 3
+        assert fwd(g, _lib.PATH_TILE_F16) == 4 and b"general local settings" in lib.qst_last_error(h)
+        # sparse frequencies: index and values needed, nnz in 0..B*D, alignment
+        B, D = 3, 1 << 10
+        for rowptr, index, nnz, want in ((0x6000, 0x7000, 10, 4), (0x6000, 0, 10, 1), (0x6000, 0x7000, -1, 2),
+                                         (0x6000, 0x7000, B * D + 1, 2), (0x6004, 0x7000, 10, 3),
+                                         (0x6000, 0x7002, 10, 3)):
+            sp = _inst()
+            sp.freqs_rowptr, sp.freqs_index, sp.freqs_nnz = rowptr, index, nnz
+            assert fwd(sp) == want, (rowptr, index, nnz)
+        # atom step: atom index, trial vector, aliasing
+        one = (_lib.QstInstance * 1)(_inst())
+        p = ctypes.c_void_p
+        assert lib.qst_atom_trial(h, one, 1, p(0x8000), p(0x9000), p(0xA000), p(0xB000), _lib.LOSS_CE, 1e-8, 0) == 4
+        assert lib.qst_atom_trial(h, one, 4, p(0x8000), p(0x9000), None, None, _lib.LOSS_NONE, 0.0, 0) == 1
+        assert lib.qst_atom_trial(h, one, -1, p(0x8000), p(0x9000), None, None, _lib.LOSS_NONE, 0.0, 0) == 1
+        assert lib.qst_atom_trial(h, one, 0, None, p(0x9000), None, None, _lib.LOSS_NONE, 0.0, 0) == 1
+        assert lib.qst_atom_trial(h, one, 0, p(0x8000), p(0x9000), p(0x9000), None, _lib.LOSS_NONE, 0.0, 0) == 1
+        assert lib.qst_atom_trial(h, one, 0, p(0x8004), p(0x9000), None, None, _lib.LOSS_NONE, 0.0, 0) == 3
+        # the iteration: schedule and stopping parameters, ranks, outputs
+        rank = ctypes.c_int32()
+
+        def solve(**kw):
+            prm = _lib.QstSolveParams(kw.get("max_slots", 10), kw.get("t_alpha", 5), kw.get("t_ref", 0),
+                                      kw.get("n_grid", 11), kw.get("rank_max", 8), 30, 20, _lib.LOSS_CE, 1e-4,
+                                      1e-3, 1e-8, 1e-3, 1e-10, 1000)
+            return lib.qst_solve(h, one, ctypes.byref(prm), None, 0, p(0xC000), p(0xD000), ctypes.byref(rank),
+                                 None, None, 0)
+
+        assert solve() == 4
+        assert solve(n_grid=0) == 1
+        assert solve(rank_max=17) == 2
+        assert solve(rank_max=2) == 2  # initial rank 4 above rank_max
+        assert solve(t_ref=10) == 1  # spectral slots without start vectors
+        assert solve(max_slots=-1) == 1
+        # Gram-form state error
+        out = ctypes.c_double()
+        assert lib.qst_state_error(h, 10, p(0x1000), p(0x2000), 4, p(0x3000), p(0x4000), 2, ctypes.byref(out), 0) == 4
+        assert lib.qst_state_error(h, 0, p(0x1000), p(0x2000), 4, p(0x3000), p(0x4000), 2, ctypes.byref(out), 0) == 2
+        assert lib.qst_state_error(h, 10, None, p(0x2000), 4, p(0x3000), p(0x4000), 2, ctypes.byref(out), 0) == 1
+        assert lib.qst_state_error(h, 10, p(0x1000), p(0x2000), 0, p(0x3000), p(0x4000), 2, ctypes.byref(out), 0) == 2
+    finally:
+        assert lib.qst_destroy(h) == 0
