@@ -39,11 +39,43 @@ def objective(atoms, weights, settings, f, kind, eps, mu):
 
 
 def slot_kind(t: int, t_alpha: int, t_ref: int) -> int:
+    """Which set of the partition (eq. iteration-partition) slot ``t`` belongs to: the
+    spectral set when ``t % t_ref == 0`` (tested first), else the coefficient set when
+    ``t % t_alpha == 0``, else the atom set; a period of 0 leaves its set empty."""
     if t_ref > 0 and t % t_ref == 0:
         return KIND_RHO
     if t_alpha > 0 and t % t_alpha == 0:
         return KIND_ALPHA
     return KIND_PSI
+
+
+def atom_direction(atoms, weights, settings, g, r: int) -> np.ndarray:
+    """Atom direction of eq. atom-direction, ``alpha_r (I - psi_r psi_r^*) G psi_r``.
+
+    With ``dL/dpsi_r^* = -alpha_r G psi_r`` (eq. atom-wirtinger-gradient; ``g`` the
+    sensitivities ``dL/dp`` of the current state) it is minus the tangent projection
+    of the atom gradient (eq. atom-projected-descent-direction)."""
+    ga, _ = born.gradients_axis(atoms, weights, settings, g)
+    return -born.tangent_project(atoms, ga)[r]
+
+
+def atom_trial(psi, d, eta: float) -> np.ndarray:
+    """Normalised proposed atom ``(psi + eta d) / ||psi + eta d||`` (eq. atom-trial)."""
+    trial = np.asarray(psi, dtype=np.complex128) + eta * np.asarray(d, dtype=np.complex128)
+    return trial / np.linalg.norm(trial)
+
+
+def coefficient_direction(atoms, weights, settings, g) -> np.ndarray:
+    """``h = A^T c = -dL/dalpha`` (eqs. h_t, weight-gradient)."""
+    _, gw = born.gradients_axis(atoms, weights, settings, g)
+    return -gw
+
+
+def coefficient_trial(weights, h, eta: float, tau: float):
+    """``P_tau(proj_Delta(alpha + eta h))`` as ``(keep, beta_check)`` (eqs.
+    coefficient-update, truncation-map)."""
+    beta = simplex.coefficient_step(weights, h, eta)
+    return simplex.prune(beta, tau)
 
 
 def run(atoms, weights, settings, f, kind=born.LOSS_CE, eps=0.0, mu=1e-3, tau=1e-3, tau_acc=1e-10,
@@ -86,12 +118,10 @@ def run(atoms, weights, settings, f, kind=born.LOSS_CE, eps=0.0, mu=1e-3, tau=1e
                     j_acc = j
                     break
         elif sk == KIND_ALPHA:
-            _, gw = born.gradients_axis(atoms, w, settings, g)
+            h = coefficient_direction(atoms, w, settings, g)
             n_oracle += 1
-            h = -gw
             for j, eta in enumerate(grid):
-                beta = simplex.coefficient_step(w, h, eta)
-                keep, bc = simplex.prune(beta, tau)
+                keep, bc = coefficient_trial(w, h, eta, tau)
                 Jn, gn = objective(atoms[keep], bc, settings, f, kind, eps, mu)
                 n_oracle += 1
                 if Jn <= J - tau_acc:
@@ -100,14 +130,11 @@ def run(atoms, weights, settings, f, kind=born.LOSS_CE, eps=0.0, mu=1e-3, tau=1e
                     break
         else:
             r = t % R
-            ga, _ = born.gradients_axis(atoms, w, settings, g)
+            d = atom_direction(atoms, w, settings, g, r)
             n_oracle += 1
-            d = -born.tangent_project(atoms, ga)[r]
             for j, eta in enumerate(grid):
-                trial = atoms[r] + eta * d
-                trial = trial / np.linalg.norm(trial)
                 new_atoms = atoms.copy()
-                new_atoms[r] = trial
+                new_atoms[r] = atom_trial(atoms[r], d, eta)
                 Jn, gn = objective(new_atoms, w, settings, f, kind, eps, mu)
                 n_oracle += 1
                 if Jn <= J - tau_acc:
