@@ -200,6 +200,27 @@ qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, con
                         void* const* atom_grad, double* const* weight_grad, double* loss,
                         qst_loss loss_kind, double eps, int project_tangent, qst_path path);
 
+/* qst_backward for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * validation and results as qst_backward; it calls no allocating routine.  Instead of
+ * the handle's workspace, the library's scratch (decoded settings, setting-batch
+ * intermediates, partial sums) lives in one fixed device array of 64 MiB per GPU, which
+ * the library holds from its first qst_create on that GPU until the process ends.
+ *   - The settings-per-batch S is lowered until the call fits the 64 MiB (an instance's
+ *     own settings_per_batch is kept as given); batches of small instances that do not
+ *     fit run one instance at a time.  Results equal qst_backward's bit for bit when the
+ *     batch sizes are the same, else to summation order.
+ *   - A call that needs more (e.g. n=20 at R=16, one setting of which is 2 x 128 MiB)
+ *     returns QST_ERR_SHAPE with the size it needs, before anything is enqueued.
+ *   - Every call on one GPU shares that GPU's array, which keeps the last call's
+ *     contents: calls that overlap in time on one GPU (other streams, other handles,
+ *     concurrent graph replays) race and must be serialised by the caller.
+ *   - Nothing has to start zeroed: every scratch entry a call reads was written by the
+ *     same call first. */
+qst_status qst_backward_static(qst_handle* h, const qst_instance* inst, int n_inst, const void* const* grad_p,
+                               void* const* atom_grad, double* const* weight_grad, double* loss,
+                               qst_loss loss_kind, double eps, int project_tangent, qst_path path);
+
 /* Trial response of an atom step (update rules for the atom slots: eqs.
  * atom-trial and pi-update).  With atom r of `inst` replaced by psi_trial,
  *     p~ = p_t + alpha_r (a(psi_trial) - a(psi_r)),   a(psi)_{b,u} = |(V_b psi)_u|^2,

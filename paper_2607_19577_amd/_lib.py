@@ -25,7 +25,7 @@ LOSS_CE, LOSS_LS, LOSS_NONE = 0, 1, 2
 # Entry points declared in include/qst.h (checked against the header by the tests).
 EXPORTS = (
     "qst_create", "qst_destroy", "qst_set_stream", "qst_status_string", "qst_last_error", "qst_plan",
-    "qst_forward", "qst_backward", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor", "qst_solve",
+    "qst_forward", "qst_backward", "qst_backward_static", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor", "qst_solve",
     "qst_state_error", "qst_build_info", "qst_profile_enable", "qst_profile_read",
 )
 
@@ -100,6 +100,7 @@ def load() -> ctypes.CDLL:
     lib.qst_forward.argtypes = [vp, P(QstInstance), ctypes.c_int, P(vp), vp, ctypes.c_int, dbl, ctypes.c_int]
     lib.qst_backward.argtypes = [vp, P(QstInstance), ctypes.c_int, P(vp), P(vp), P(vp), vp, ctypes.c_int, dbl,
                                  ctypes.c_int, ctypes.c_int]
+    lib.qst_backward_static.argtypes = lib.qst_backward.argtypes
     lib.qst_atom_trial.argtypes = [vp, P(QstInstance), ctypes.c_int, vp, vp, vp, vp, ctypes.c_int, dbl,
                                    ctypes.c_int]
     lib.qst_reweight_simplex.argtypes = [vp, vp, vp, ctypes.c_int, dbl, dbl, vp, vp, vp]

@@ -18,7 +18,7 @@ from ._lib import (LOSS_CE, LOSS_LS, LOSS_NONE, PATH_AUTO, PATH_BUTTERFLY_BF16, 
                    QstSolveParams)
 
 __all__ = [
-    "Handle", "Instance", "qst_forward", "qst_backward", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor",
+    "Handle", "Instance", "qst_forward", "qst_backward", "qst_backward_static", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor",
     "qst_plan", "qst_solve", "qst_state_error", "SolveParams",
     "LOSS_CE", "LOSS_LS", "LOSS_NONE", "PATH_AUTO", "PATH_BUTTERFLY_F32", "PATH_BUTTERFLY_F64", "PATH_PLAIN_F32",
     "PATH_TILE_F16", "PATH_TILE_BF16", "PATH_BUTTERFLY_BF16", "QSTError",
@@ -188,7 +188,7 @@ def qst_forward(h: Handle, insts: Sequence[Instance], want_probs: bool = True, l
 
 def qst_backward(h: Handle, insts: Sequence[Instance], grad_p: Optional[Sequence[torch.Tensor]] = None,
                  loss: int = LOSS_CE, eps: float = 1e-8, project_tangent: bool = False, path: int = PATH_AUTO,
-                 want_loss: bool = True, out: Optional[List[torch.Tensor]] = None):
+                 want_loss: bool = True, out: Optional[List[torch.Tensor]] = None, _entry: str = "qst_backward"):
     """Fused forward + adjoint.  Returns ``(loss [n] float64 or None, atom_grads, weight_grads)``."""
     arr = _structs(insts, path)
     n = len(insts)
@@ -206,9 +206,19 @@ def qst_backward(h: Handle, insts: Sequence[Instance], grad_p: Optional[Sequence
         loss = LOSS_NONE
         want_loss = False
     lt = torch.empty(n, dtype=torch.float64, device=dev) if want_loss else None
-    _lib.check(h.lib.qst_backward(h.h, arr, n, gpp, agp, wgp, _ptr(lt), loss, float(eps), int(project_tangent), path),
-               h.h)
+    _lib.check(getattr(h.lib, _entry)(h.h, arr, n, gpp, agp, wgp, _ptr(lt), loss, float(eps), int(project_tangent),
+                                      path), h.h)
     return lt, ag, wg
+
+
+def qst_backward_static(h: Handle, insts: Sequence[Instance], grad_p: Optional[Sequence[torch.Tensor]] = None,
+                        loss: int = LOSS_CE, eps: float = 1e-8, project_tangent: bool = False, path: int = PATH_AUTO,
+                        want_loss: bool = True, out: Optional[List[torch.Tensor]] = None):
+    """``qst_backward`` through the no-allocation entry point (the library's scratch is a fixed
+    64 MiB device array per GPU; calls that need more raise QST_ERR_SHAPE).  The outputs are
+    allocated here unless ``out`` is given; the library itself allocates nothing."""
+    return qst_backward(h, insts, grad_p, loss, eps, project_tangent, path, want_loss, out,
+                        _entry="qst_backward_static")
 
 
 def qst_atom_trial(h: Handle, inst: Instance, r: int, psi_trial: torch.Tensor, probs_t: Optional[torch.Tensor],

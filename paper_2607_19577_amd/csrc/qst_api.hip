@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -18,6 +19,13 @@
 #include "qst_internal.hpp"
 
 using qst::Geometry;
+
+// Scratch of the no-allocation backward (qst_backward_static): a fixed device array, one
+// copy per GPU, held until the process ends.  In host code this name is only a symbol
+// for hipGetSymbolAddress; the device address of each GPU's copy is looked up once per
+// device (scratch_address) and only that address is passed to kernels.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 struct qst_handle {
   int device = 0;
@@ -44,6 +52,9 @@ struct qst_handle {
   std::vector<Mark> marks;
   int open_kind = -1;
   hipEvent_t open_ev = nullptr;
+  // no-allocation mode (qst_backward_static): ws points at the device's static scratch
+  void* static_scratch = nullptr;  // this device's copy of `scratch` (from qst_create)
+  bool static_ws = false;
 };
 
 namespace {
@@ -69,7 +80,7 @@ bool capturing(hipStream_t st) {
 
 // Bracket the next launch(es) of one stage kind.
 void prof_begin(qst_handle* h, int kind) {
-  if (!h->prof || capturing(h->stream)) return;
+  if (!h->prof || h->static_ws || capturing(h->stream)) return;
   hipEvent_t e = prof_event(h);
   if (!e) return;
   hipEventRecord(e, h->stream);
@@ -78,7 +89,7 @@ void prof_begin(qst_handle* h, int kind) {
 }
 
 void prof_end(qst_handle* h) {
-  if (!h->prof || h->open_kind < 0 || capturing(h->stream)) return;
+  if (!h->prof || h->static_ws || h->open_kind < 0 || capturing(h->stream)) return;
   hipEvent_t e = prof_event(h);
   if (!e) return;
   hipEventRecord(e, h->stream);
@@ -101,6 +112,10 @@ qst_status set_err(qst_handle* h, qst_status s, const std::string& msg) {
 
 qst_status ensure_ws(qst_handle* h, size_t bytes) {
   if (bytes <= h->ws_bytes) return QST_OK;
+  if (h->static_ws)
+    return set_err(h, QST_ERR_SHAPE, "the call needs " + std::to_string(bytes) +
+                                         " bytes of scratch; qst_backward_static holds " +
+                                         std::to_string(kStaticScratchBytes) + " bytes");
   if (capturing(h->stream))
     return set_err(h, QST_ERR_CAPTURE, "workspace must grow while the stream is capturing; call qst_plan first");
   if (h->ws) {
@@ -363,6 +378,23 @@ int batch_size(const qst_handle* h, const Geometry& g, const qst_instance& in, q
   return default_S(g);
 }
 
+// No-allocation mode: the largest batch size up to S whose workspace fits the static
+// scratch (1 if none does; the call then fails in ensure_ws).  A caller's own batch size
+// is kept as given.
+int fit_static_S(const qst_handle* h, Geometry g, const qst_instance& in, int S, qst_path path, size_t base) {
+  if (!h->static_ws || in.settings_per_batch > 0) return S;
+  int lo = 1, hi = S;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    set_grid(const_cast<qst_handle*>(h), g, mid);
+    if (layout_ws(g, mid, path, false, base).total <= h->ws_bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, size_t* ws_end = nullptr) {
   const qst_instance& in = *rs.in;
   const qst_path path = rs.path;
@@ -370,7 +402,8 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   qst_status st = make_geometry(h, in.n_qubits, in.rank, in.n_settings, path, g);
   if (st != QST_OK) return st;
   mark(g, in);
-  const int S = batch_size(h, g, in, path, rs.S_override);
+  const int S = rs.S_override > 0 ? batch_size(h, g, in, path, rs.S_override)
+                                  : fit_static_S(h, g, in, batch_size(h, g, in, path, 0), path, ws_base);
   set_grid(h, g, S);
   const WsLayout L = layout_ws(g, S, path, false, ws_base);
   if (ws_end) *ws_end = L.total;
@@ -732,6 +765,16 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
         single.push_back(part[0]);
         continue;
       }
+      if (h->static_ws) {
+        // a batch whose buffers do not fit the static scratch runs one instance at a time
+        BatchLayout L;
+        qst_status st = batch_layout(h, part, part[0]->adjoint, 0, L);
+        if (st != QST_OK) return st;
+        if (L.total > h->ws_bytes) {
+          single.insert(single.end(), part.begin(), part.end());
+          continue;
+        }
+      }
       if (need) {
         BatchLayout L;
         qst_status st = batch_layout(h, part, part[0]->adjoint, 0, L);
@@ -749,7 +792,7 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
       qst_status st = make_geometry(h, r->in->n_qubits, r->in->rank, r->in->n_settings, r->path, g);
       if (st != QST_OK) return st;
       mark(g, *r->in);
-      const int S = batch_size(h, g, *r->in, r->path, 0);
+      const int S = fit_static_S(h, g, *r->in, batch_size(h, g, *r->in, r->path, 0), r->path, 0);
       set_grid(h, g, S);
       *need = std::max(*need, layout_ws(g, S, r->path, false).total);
       continue;
@@ -820,6 +863,26 @@ std::vector<double> proj_simplex(const std::vector<double>& v) {
 }
 
 }  // namespace
+
+// Device address of `scratch` on `device` (which must be current): looked up once per device
+// and kept until the process ends.
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_addr;
+
+static hipError_t scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  g_scratch_addr.emplace(device, p);
+  *out = p;
+  return hipSuccess;
+}
 
 // Internal access for the host-orchestrated iteration (qst_solve.hip); not exported.
 #define QST_HIDDEN __attribute__((visibility("hidden")))
@@ -908,6 +971,7 @@ qst_status qst_create(int device, void* hip_stream, qst_handle** out) {
   *h->hflag = 0;
   hipMemset(h->dflag, 0, sizeof(int));
   hipDeviceSynchronize();
+  if (scratch_address(device, &h->static_scratch) != hipSuccess) h->static_scratch = nullptr;
   *out = h;
   return QST_OK;
 }
@@ -1094,9 +1158,9 @@ qst_status qst_forward(qst_handle* h, const qst_instance* inst, int n_inst, void
   return QST_OK;
 }
 
-qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, const void* const* grad_p,
-                        void* const* atom_grad, double* const* weight_grad, double* loss, qst_loss loss_kind,
-                        double eps, int project_tangent, qst_path path) {
+static qst_status backward_impl(qst_handle* h, const qst_instance* inst, int n_inst, const void* const* grad_p,
+                                void* const* atom_grad, double* const* weight_grad, double* loss, qst_loss loss_kind,
+                                double eps, int project_tangent, qst_path path) {
   qst_status st = common_checks(h, inst, n_inst, path);
   if (st != QST_OK) return st;
   path = resolve(path);
@@ -1135,10 +1199,45 @@ qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, con
     rs.project_tangent = project_tangent;
     rs.adjoint = true;
   }
+  if (h->static_ws) {
+    // everything must fit the static scratch before anything is enqueued
+    size_t need = 0;
+    st = run_call(h, specs, &need);
+    if (st != QST_OK) return st;
+    st = ensure_ws(h, need);
+    if (st != QST_OK) return st;
+  }
   st = run_call(h, specs);
   if (st != QST_OK) return st;
   post_flag(h);
   return QST_OK;
+}
+
+qst_status qst_backward(qst_handle* h, const qst_instance* inst, int n_inst, const void* const* grad_p,
+                        void* const* atom_grad, double* const* weight_grad, double* loss, qst_loss loss_kind,
+                        double eps, int project_tangent, qst_path path) {
+  return backward_impl(h, inst, n_inst, grad_p, atom_grad, weight_grad, loss, loss_kind, eps, project_tangent, path);
+}
+
+qst_status qst_backward_static(qst_handle* h, const qst_instance* inst, int n_inst, const void* const* grad_p,
+                               void* const* atom_grad, double* const* weight_grad, double* loss, qst_loss loss_kind,
+                               double eps, int project_tangent, qst_path path) {
+  if (!h) return QST_ERR_INVALID_ARG;
+  if (h->device >= 0 && h->static_scratch == nullptr)
+    return set_err(h, QST_ERR_DEVICE, "the static scratch of this device has no address (hipGetSymbolAddress failed)");
+  // The handle's own workspace is set aside for the call and the device's static scratch
+  // takes its place; ensure_ws then refuses to grow instead of allocating.
+  void* const ws = h->ws;
+  const size_t ws_bytes = h->ws_bytes;
+  h->ws = h->static_scratch;
+  h->ws_bytes = h->device >= 0 ? kStaticScratchBytes : 0;
+  h->static_ws = true;
+  const qst_status st =
+      backward_impl(h, inst, n_inst, grad_p, atom_grad, weight_grad, loss, loss_kind, eps, project_tangent, path);
+  h->static_ws = false;
+  h->ws = ws;
+  h->ws_bytes = ws_bytes;
+  return st;
 }
 
 qst_status qst_atom_trial(qst_handle* h, const qst_instance* inst, int r, const void* psi_trial,
