@@ -41,6 +41,7 @@ struct qst_handle {
   bool flag_pending = false;
   std::map<std::tuple<int, int, int, int>, int> tuned_S;  // (n, R, B, path) -> settings per batch
   std::map<std::tuple<int, int, int, int>, int> occupancy;  // (n_lo, n_hi > 0, R, elem) -> low-stage WGs per CU
+  std::map<std::pair<int, int>, int> oc_occupancy;           // (n, adjoint) -> on-chip pass WGs per CU
   // stage timing
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -745,10 +746,221 @@ qst_status run_batch(qst_handle* h, const std::vector<const RunSpec*>& rs) {
 
 // Runs the instances of one call: batches of small instances (equal n), the rest
 // one by one.  `need` (optional) receives the workspace the call uses instead.
+// ---------------------------------------------------------------- on-chip path (n = 11..14)
+// Instances whose (setting, atom) vector fits one work-group run their whole rotation on
+// chip (qst_onchip.hip): pass F forms p, the loss and 2^-k g per setting with the atoms
+// looped, pass A recomputes each atom's rotation per setting and sums the adjoint over a
+// slice of settings in registers.  No intermediate amplitudes cross HBM.
+bool oc_eligible(const RunSpec& r) {
+  const qst_instance& in = *r.in;
+  if (resolve(r.path) != QST_PATH_BUTTERFLY_F32) return false;
+  if (in.unitaries || in.freqs_rowptr || in.settings_per_batch > 0) return false;
+  if (in.n_qubits < 11 || in.n_qubits > 14) return false;
+  // the outcome rows are read and written four values at a time
+  auto a16 = [](const void* p) { return p == nullptr || aligned(p, 16); };
+  return a16(in.freqs) && a16(in.probs_base) && a16(r.probs) && a16(r.grad_p) && a16(r.gneg) && a16(r.atom_grad) &&
+         a16(in.atoms);
+}
+
+// QST_ONCHIP (environment, read once): 0 never, 1 for every eligible instance; unset: when
+// the atoms of a setting do not fit one low-stage work-group (R 2^n > 2^14).
+int env_onchip() {
+  static const int v = [] {
+    const char* e = std::getenv("QST_ONCHIP");
+    return e ? std::atoi(e) : -1;
+  }();
+  return v;
+}
+
+bool oc_use(const RunSpec& r) {
+  if (!oc_eligible(r)) return false;
+  const int e = env_onchip();
+  if (e == 0) return false;
+  if (e == 1) return true;
+  return ((long long)r.in->rank << r.in->n_qubits) > 16384;
+}
+
+// Slicing of pass A.  An instance is cut into enough slices to give every resident work-group
+// one item when it runs alone, but no slice has fewer than QST_OC_SLICE_MIN settings
+// (environment, default 16), which bounds the partial sums written to HBM at 16 / S_min bytes
+// per (setting, atom) amplitude.  The rule depends on the instance alone, so a call with
+// several instances gives each the same bits as a call with it alone.
+int env_oc_slice_min() {
+  static const int v = [] {
+    const char* e = std::getenv("QST_OC_SLICE_MIN");
+    const int x = e ? std::atoi(e) : 0;
+    return x > 0 ? x : 16;
+  }();
+  return v;
+}
+
+// Values per thread of the on-chip passes: QST_OC_LOGV (environment, read once) if it names a
+// supported shape, else 2^5.
+int oc_logv(int n) {
+  static const int v = [] {
+    const char* e = std::getenv("QST_OC_LOGV");
+    return e ? std::atoi(e) : 0;
+  }();
+  return qst::oc_shape_ok(n, v) ? v : 5;
+}
+
+int oc_occ(qst_handle* h, int n, int logv, bool adj) {
+  const auto key = std::make_pair(n * 16 + logv, adj ? 1 : 0);
+  auto it = h->oc_occupancy.find(key);
+  if (it == h->oc_occupancy.end()) it = h->oc_occupancy.emplace(key, qst::oc_blocks_per_cu(n, logv, adj)).first;
+  return it->second;
+}
+
+qst_status run_onchip(qst_handle* h, std::vector<const RunSpec*> rs, size_t* need) {
+  // Instances grouped by n (one launch of each pass per n), larger ones first.
+  std::stable_sort(rs.begin(), rs.end(), [](const RunSpec* a, const RunSpec* b) {
+    if (a->in->n_qubits != b->in->n_qubits) return a->in->n_qubits > b->in->n_qubits;
+    return (long long)a->in->n_settings * a->in->rank > (long long)b->in->n_settings * b->in->rank;
+  });
+  const int count = (int)rs.size();
+  std::vector<qst::OcInst> tab(count);
+  size_t o = al256((size_t)count * sizeof(qst::OcInst));
+  std::vector<size_t> off_pc(count), off_G(count), off_P(count), off_part(count);
+  struct Group {
+    int n, logv, k0, k1, itemsF, itemsA;
+  };
+  std::vector<Group> groups;
+  int rmax = 1, sum_blocks = 0;
+  bool any_rows = false, any_tan = false;
+  for (int k = 0; k < count; ++k) {
+    const RunSpec& r = *rs[k];
+    const qst_instance& in = *r.in;
+    qst::OcInst& a = tab[k];
+    a = qst::OcInst{};
+    const int n = in.n_qubits, R = in.rank, B = in.n_settings;
+    const long long D = 1ll << n;
+    const int logv = oc_logv(n);
+    const int vpw = qst::oc_threads_of(n, logv) >> (n - logv);
+    if (groups.empty() || groups.back().n != n) groups.push_back(Group{n, logv, k, k, 0, 0});
+    Group& gr = groups.back();
+    gr.k1 = k + 1;
+    a.n = n;
+    a.R = R;
+    a.B = B;
+    a.eps = r.eps;
+    a.loss_kind = r.grad_p ? 2 : (int)r.loss_kind;
+    a.ntile = (R + vpw - 1) / vpw;
+    a.sF = vpw;
+    const bool fpass = r.grad_p == nullptr;  // the caller's dL/dp replaces pass F
+    const int nF = fpass ? (B + a.sF - 1) / a.sF : 0;
+    if (r.adjoint) {
+      const int resident = h->num_cu * oc_occ(h, n, logv, true);
+      const int fill = (resident + a.ntile - 1) / a.ntile;
+      const int most = std::max(1, B / env_oc_slice_min());
+      const int nA0 = std::max(1, std::min(fill, most));
+      const int sA = std::max((B + nA0 - 1) / nA0, a.sF);
+      a.sA = sA;
+      a.nA = (B + sA - 1) / sA;
+    } else {
+      a.sA = B;
+      a.nA = 0;
+    }
+    a.nslots = std::max(nF, std::max(a.nA, 1));
+    a.itemF0 = gr.itemsF;
+    gr.itemsF += nF;
+    a.itemA0 = gr.itemsA;
+    if (r.adjoint) gr.itemsA += a.nA * a.ntile;
+    a.tangent = r.adjoint && r.project_tangent ? 1 : 0;
+    rmax = std::max(rmax, R);
+    a.loss = (r.grad_p == nullptr && r.loss_kind != QST_LOSS_NONE) ? r.loss : nullptr;
+    a.wgrad = r.adjoint ? r.weight_grad : nullptr;
+    any_rows |= a.loss != nullptr || a.wgrad != nullptr;
+    any_tan |= a.tangent != 0;
+    off_pc[k] = o;
+    o = al256(o + (size_t)B * 8);
+    off_G[k] = o;
+    if (r.adjoint && fpass) o = al256(o + (size_t)B * D * 4);
+    off_P[k] = o;
+    if (r.adjoint && a.nA > 1) o = al256(o + (size_t)a.nA * R * D * 8);
+    off_part[k] = o;
+    o = al256(o + (size_t)(R + 1) * a.nslots * 8);
+    a.sumB0 = sum_blocks;
+    if (r.adjoint && a.nA > 1) sum_blocks += (int)(((long long)R * D + 1023) / 1024);
+  }
+  if (need) {
+    *need = std::max(*need, o);
+    return QST_OK;
+  }
+  qst_status st = ensure_ws(h, o);
+  if (st != QST_OK) return st;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(h->ws);
+  hipStream_t s = h->stream;
+  qst::OcInst* dtab = reinterpret_cast<qst::OcInst*>(ws);
+  for (int k = 0; k < count; ++k) {
+    const RunSpec& r = *rs[k];
+    const qst_instance& in = *r.in;
+    qst::OcInst& a = tab[k];
+    a.atoms = in.atoms;
+    a.alpha = in.weights;
+    a.pc = reinterpret_cast<const uint64_t*>(ws + off_pc[k]);
+    a.freqs = r.grad_p ? nullptr : in.freqs;
+    a.grad_p = reinterpret_cast<const float*>(r.grad_p);
+    a.pbase = reinterpret_cast<const float*>(in.probs_base);
+    a.probs = reinterpret_cast<float*>(r.probs);
+    a.gneg = reinterpret_cast<float*>(r.gneg);
+    a.G = (r.adjoint && r.grad_p == nullptr) ? reinterpret_cast<float*>(ws + off_G[k]) : nullptr;
+    a.P = (r.adjoint && a.nA > 1) ? reinterpret_cast<float2*>(ws + off_P[k]) : nullptr;
+    a.grad = r.adjoint ? reinterpret_cast<float2*>(r.atom_grad) : nullptr;
+    a.part = reinterpret_cast<double*>(ws + off_part[k]);
+  }
+  prof_begin(h, PK_DECODE);
+  for (int c0 = 0; c0 < count; c0 += qst::kOcChunk) {
+    qst::OcChunk ch{};
+    ch.first = c0;
+    ch.count = std::min(qst::kOcChunk, count - c0);
+    for (int i = 0; i < ch.count; ++i) ch.a[i] = tab[c0 + i];
+    QST_HIP(qst::launch_oc_stage(ch, dtab, s));
+  }
+  for (int k = 0; k < count; ++k)
+    QST_HIP(qst::launch_decode(rs[k]->in->settings, tab[k].B, tab[k].n, reinterpret_cast<uint64_t*>(ws + off_pc[k]),
+                               h->dflag, s));
+  prof_end(h);
+  for (const Group& gr : groups) {
+    if (gr.itemsF > 0) {
+      const int grid = (int)std::min<long long>(gr.itemsF, (long long)h->num_cu * oc_occ(h, gr.n, gr.logv, false));
+      prof_begin(h, PK_HI_FWD);
+      QST_HIP(qst::launch_oc_pass(gr.n, gr.logv, false, dtab, gr.k0, gr.k1, gr.itemsF, grid, s));
+      prof_end(h);
+    }
+    if (gr.itemsA > 0) {
+      const int grid = (int)std::min<long long>(gr.itemsA, (long long)h->num_cu * oc_occ(h, gr.n, gr.logv, true));
+      prof_begin(h, PK_LO);
+      QST_HIP(qst::launch_oc_pass(gr.n, gr.logv, true, dtab, gr.k0, gr.k1, gr.itemsA, grid, s));
+      prof_end(h);
+    }
+  }
+  if (sum_blocks > 0 || any_rows || any_tan) {
+    prof_begin(h, PK_REDUCE);
+    QST_HIP(qst::launch_oc_finish(dtab, count, sum_blocks, rmax, any_rows, any_tan, s));
+    prof_end(h);
+  }
+  return QST_OK;
+}
+
 qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* need = nullptr) {
   std::map<int, std::vector<const RunSpec*>> groups;
   std::vector<const RunSpec*> single;
+  std::vector<const RunSpec*> onchip;
+  for (const RunSpec& r : specs)
+    if (oc_use(r)) onchip.push_back(&r);
+  if (!onchip.empty() && h->static_ws) {
+    // without allocation the on-chip buffers must fit the static scratch, else the staged path runs
+    size_t oc_need = 0;
+    qst_status st = run_onchip(h, onchip, &oc_need);
+    if (st != QST_OK) return st;
+    if (oc_need > h->ws_bytes) onchip.clear();
+  }
+  if (!onchip.empty()) {
+    qst_status st = run_onchip(h, onchip, need);
+    if (st != QST_OK) return st;
+  }
   for (const RunSpec& r : specs) {
+    if (std::find(onchip.begin(), onchip.end(), &r) != onchip.end()) continue;
     Geometry g;
     qst_status st = make_geometry(h, r.in->n_qubits, r.in->rank, r.in->n_settings, r.path, g);
     if (st != QST_OK) return st;

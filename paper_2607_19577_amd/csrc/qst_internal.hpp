@@ -188,6 +188,54 @@ hipError_t launch_convert(const void* src, int src_c64, void* dst, int dst_c64, 
                           hipStream_t st);
 hipError_t launch_axpy_c(void* y, int y_c64, const void* x, int x_c64, long long n, double a, hipStream_t st);
 
+// On-chip path (qst_onchip.hip): states of 2^11 .. 2^14 amplitudes, FP32, Pauli settings,
+// dense data.  One entry per instance of a call, in device memory (written by k_oc_stage
+// from by-value chunks).  Pass F items: settings [j sF, (j+1) sF) of instance k; pass A items:
+// slice j / ntile (settings [slice sA, (slice+1) sA)), atoms [tile VPW, (tile+1) VPW) with
+// tile = j % ntile.  Loss partials go to part[0][j] (j < nF = nslots), weight-gradient
+// partials to part[1+r][slice] (slices < nA <= nF; pass F zeroes the rest).
+struct OcInst {
+  const void* atoms;    // [R][D] complex64
+  const double* alpha;  // [R]
+  const uint64_t* pc;   // decoded settings [B]
+  const float* freqs;   // [B][D] or null
+  const float* grad_p;  // [B][D] or null: caller's dL/dp (then pass F is skipped)
+  const float* pbase;   // [B][D] or null
+  float* probs;         // [B][D] or null
+  float* gneg;          // [B][D] or null: receives -dL/dp
+  float* G;             // [B][D] workspace: 2^-k dL/dp of pass F (null with grad_p)
+  float2* P;            // [nA][R][D] workspace: slice partials (unused when nA == 1)
+  float2* grad;         // [R][D] atom gradient (null: forward only)
+  double* part;         // [(R+1)][nslots] or null
+  double* loss;         // device scalar or null
+  double* wgrad;        // [R] or null
+  long long nslots;
+  double eps;
+  int n, R, B, loss_kind;
+  int sF, sA, nA, ntile;
+  int itemF0, itemA0, sumB0, tangent;
+};
+static_assert(sizeof(OcInst) % 4 == 0, "staged as 32-bit words");
+constexpr int kOcChunk = 16;
+struct OcChunk {
+  int count;
+  int first;
+  OcInst a[kOcChunk];
+};
+static_assert(sizeof(OcChunk) <= 4096, "kernel argument block too large");
+// 2^logv values per thread (5 for n = 11..14, or 4 for n = 13, 14: twice the threads).
+bool oc_shape_ok(int n, int logv);
+size_t oc_lds_bytes(int n, int logv);
+int oc_threads_of(int n, int logv);
+int oc_blocks_per_cu(int n, int logv, bool adj);
+// Pass F (adj = false) or A over items [0, total) of instances [k0, k1) (all of n qubits).
+hipError_t launch_oc_pass(int n, int logv, bool adj, const OcInst* tab, int k0, int k1, int total, int grid,
+                          hipStream_t st);
+hipError_t launch_oc_stage(const OcChunk& c, OcInst* tab, hipStream_t st);
+// Slice sums (sum_blocks > 0), loss and weight-gradient rows (rows), tangent projection.
+hipError_t launch_oc_finish(const OcInst* tab, int count, int sum_blocks, int rmax, bool rows, bool tangent,
+                            hipStream_t st);
+
 // Register bits per thread of the low stage (2^logv values): 5, or 4 in the forward pass
 // over staged chunks of 2^12 and more outcomes (ranks up to 4: twice the wavefronts).
 constexpr int lo_logv_of(int n_lo, bool staged, bool adjoint) {
