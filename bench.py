@@ -76,6 +76,24 @@ def _cpu_grads(task):
     return ga[0], float(gw[0])
 
 
+def host_info() -> dict:
+    """CPU model and core counts of the host the oracle runs on, read at run time."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "host_logical_cpus": os.cpu_count() or 1, "usable_cpus": usable}
+
+
 def cpu_baseline(atoms, w, s, B, shots, n_sample: int, seed: int):
     """The FP64 oracle (per-axis tier) on an instance made of the first n_sample settings, all
     atoms: probabilities, loss and sensitivities, then the adjoint, split into (setting, atom)
@@ -88,7 +106,10 @@ def cpu_baseline(atoms, w, s, B, shots, n_sample: int, seed: int):
         synth.make_rng(seed + 1), 4), shots)
     _CPU.update(atoms=atoms.astype(np.complex128), w=w, s=s[:n_sample])
     tasks = [(b, r) for b in range(n_sample) for r in range(R)]
-    cores = max(1, min(16, os.cpu_count() or 1, len(tasks)))
+    host = host_info()
+    # the pool covers the usable CPUs, at most 16 processes (the CPU share of one GPU of the
+    # host the benchmark runs on)
+    cores = max(1, min(16, host["usable_cpus"], len(tasks)))
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores, initializer=_cpu_init) as pool:
@@ -106,7 +127,7 @@ def cpu_baseline(atoms, w, s, B, shots, n_sample: int, seed: int):
             gw[r] += x
     dt = time.perf_counter() - t0
     amps = n_sample * R * D
-    rec = dict(value=amps / dt, unit="amplitudes/s", cores=cores, kind="oracle",
+    rec = dict(value=amps / dt, unit="amplitudes/s", cores=cores, kind="oracle", **host,
                sample=f"{n_sample} of {B} settings x {R} atoms x D={D} (an instance of those settings): "
                       f"FP64 per-axis oracle probabilities, CE loss and sensitivities, adjoint; {dt:.1f} s "
                       f"wall on {cores} processes")
@@ -172,18 +193,83 @@ def solve_extra(api, h, dev, seed: int, slots: int = 100):
            "oracle_calls": res["oracle_calls"], "rank_final": res["rank"],
            "J_first_slot": round(float(hist[0, 2]), 6), "J_final": round(float(hist[-1, 2]), 6),
            "e_rho_initial": round(e0, 4), "e_rho_final": round(e1, 4)}
-    # Which moves are enabled (ablation section): atom steps only, atom and coefficient steps, and
-    # the full schedule, from the same start, each for the same number of slots (no early stop).
-    abl = {}
-    for name, ta, tr in (("atom_only", 0, 0), ("atom_coeff", 5, 0), ("full", 5, 10)):
-        pv = api.SolveParams(max_slots=slots, t_alpha=ta, t_ref=tr, rank_max=Rmax, n_lanczos=30, stop_window=0)
-        rv = api.qst_solve(h, api.Instance(atoms0, w0, s, f), pv, v0s)
-        ev = api.qst_state_error(h, rv["atoms"].contiguous(), rv["weights"].contiguous(), truth, wt)
-        abl[name] = {"slots": rv["slots"], "accepted": int(rv["history"][:, 4].sum()),
-                     "oracle_calls": rv["oracle_calls"], "rank_final": rv["rank"],
-                     "J_final": round(float(rv["history"][-1, 2]), 6), "e_rho_final": round(ev, 4)}
-    out["ablation"] = abl
     return out
+
+
+VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak
+
+
+def onchip_extra(api, h, dev, seed: int, steps: int = 20, warmup: int = 3):
+    """The n=14, R=8, B=1000 workload (1e5 shots), where one (setting, atom) vector of 2^14
+    amplitudes fits a work-group and the whole rotation runs on chip: the same step as the
+    headline (decode, fused forward + adjoint with CE loss, weight gradient and tangent
+    projection, FP64 coefficient step), event-timed, with the two passes' times, the modelled HBM
+    bytes, a roofline against the FP32 vector peak (the path is bound by vector work and LDS
+    transposes, not HBM) and errors against the oracle on a sample of settings."""
+    import torch
+
+    from oracle import born
+
+    wl = WORKLOADS["n14_r8_b1000"]
+    n, R, B, shots = wl["n"], wl["R"], wl["B"], wl["shots"]
+    D = 1 << n
+    rng = synth.make_rng(seed)
+    atoms = synth.haar_atoms(rng, R, D, dtype=np.complex64)
+    w = synth.dirichlet_weights(rng, R)
+    s = synth.random_settings(rng, B, n)
+    freqs = synth.porter_thomas_freqs_torch(seed + 1, B, D, synth.dirichlet_weights(rng, wl["R_true"]), shots, dev)
+    inst = api.Instance(torch.from_numpy(atoms).to(dev), torch.from_numpy(w).to(dev), torch.from_numpy(s).to(dev),
+                        freqs)
+    grad = torch.empty_like(inst.atoms)
+
+    def step():
+        _, _, wg = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, project_tangent=True, out=[grad])
+        api.qst_reweight_simplex(h, inst.weights, wg[0], -0.5, 1e-3)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile(True)
+    h.profile_read(reset=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    stages = h.profile_read(reset=True)
+    h.profile(False)
+    step_ms = float(np.median(ms))
+    amps = B * R * D
+    tflops = 68.0 * amps / (step_ms * 1e-3) / 1e12  # the method's 68 flop per amplitude (fwd + adjoint)
+    # HBM bytes the step must move: frequencies read, 2^-k dL/dp written and read back (its re-reads by
+    # the other atom tiles of a slice come from L2), the slice partials written and summed, the atoms
+    # and the gradient
+    slices = max(1, min(256 // R, B // 16))
+    hbm = 3 * B * D * 4 + 2 * slices * R * D * 8 + 3 * R * D * 8
+    sample = [0, 333, 666, 999]
+    sub_s = s[sample]
+    sub_f = synth.porter_thomas_freqs(synth.make_rng(seed + 2), len(sample), D,
+                                      synth.dirichlet_weights(synth.make_rng(seed + 3), 4), shots)
+    sub = api.Instance(inst.atoms, inst.weights, torch.from_numpy(sub_s).to(dev), torch.from_numpy(sub_f).to(dev))
+    lt_s, ag_s, wg_s = api.qst_backward(h, [sub], loss=api.LOSS_CE, eps=1e-8)
+    torch.cuda.synchronize()
+    Lr, _, gar, gwr = born.forward_backward(atoms.astype(np.complex128), w, sub_s, sub_f.astype(np.float64),
+                                            born.LOSS_CE, 1e-8)
+    errs = {"loss": _relerr(float(lt_s[0]), Lr), "weight_grad": _relerr(wg_s[0].cpu().numpy(), gwr),
+            "atom_grad": _relerr(ag_s[0].cpu().numpy(), gar)}
+    return {"workload": f"n={n}, R={R}, B={B}, {shots} shots/setting, complex64, cross-entropy",
+            "ms_per_step": round(step_ms, 4), "amplitudes_per_s": amps / (step_ms * 1e-3),
+            "pass_ms_per_step": {"forward_atoms_looped": round(stages["hi_fwd"][1] / steps, 4),
+                                 "adjoint_slices": round(stages["lo_fused"][1] / steps, 4),
+                                 "sums_reductions_tangent": round(stages["reduce"][1] / steps, 4)},
+            "model_hbm_bytes_per_step": hbm, "model_GBps": round(hbm / (step_ms * 1e-3) / 1e9, 1),
+            "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
+                         "flops": "68 per (setting, atom) amplitude, the method's forward + adjoint"},
+            "errors_vs_oracle": {"settings": len(sample), **{k: float(f"{v:.3e}") for k, v in errs.items()},
+                                 "tol": 1e-5, "pass": all(v <= 1e-5 for v in errs.values())}}
 
 
 def uneven_batch_extra(api, h, dev, seed: int, reps: int = 5):
@@ -256,7 +342,7 @@ def main():
                          "BF16 intermediates (1e-2 variant)")
     ap.add_argument("--batch", type=int, default=0, help="settings per batch (0: library default or --autotune)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only a 1 GiB device copy (counter scale)")
-    ap.add_argument("--only", choices=["uneven64", "solve"], default=None,
+    ap.add_argument("--only", choices=["uneven64", "solve", "onchip"], default=None,
                     help="run only one extra (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -276,6 +362,8 @@ def main():
         h = api.Handle(0)
         if args.only == "uneven64":
             res = uneven_batch_extra(api, h, dev, seed + 21)
+        elif args.only == "onchip":
+            res = onchip_extra(api, h, dev, seed + 41)
         else:
             res = solve_extra(api, h, dev, seed + 31)
         print(json.dumps({args.only: res}), flush=True)
@@ -500,6 +588,7 @@ def main():
         extras["refactor_R_out"] = int(res["R"][0])
 
     if not args.no_extras:
+        extras["n14_r8_b1000_onchip"] = onchip_extra(api, h, dev, seed + 41)
         extras["uneven64"] = uneven_batch_extra(api, h, dev, seed + 21)
         extras["solve"] = solve_extra(api, h, dev, seed + 31)
 

@@ -5,11 +5,11 @@ Tolerance 1e-2 (norm-wise, and element-wise scaled by the largest reference elem
 for probabilities, loss, atom and weight gradients.  The BF16 path splits each
 amplitude into two BF16 parts and is checked at 1e-4 as well; the FP16 path scales
 each 16x16 block before rounding and is checked at 3e-3.  At the full n=20, R=16
-shape the tile paths are compared with the FP32 butterfly path on a setting subset.
+shape every path is compared with the oracle on three sampled settings.
 
 The staged butterfly path with BF16 intermediates (FP32 arithmetic, the setting-batch
 amplitudes X and W stored in BF16) is checked at 1e-2, including several batches,
-batched small instances and the full n=20, R=16 shape on a setting subset.
+batched small instances and the full n=20, R=16 shape on sampled settings.
 """
 import numpy as np
 import pytest
@@ -80,30 +80,34 @@ def test_tile_path_least_squares(h, path_name):
         assert close(ga[r], gar[r], tol), (r, rel(ga[r], gar[r]))
 
 
+@pytest.fixture(scope="module")
+def n20_sample():
+    """n=20, R=16 on three settings with Porter-Thomas frequencies, and the oracle's results."""
+    rng = synth.make_rng(960)
+    n, R, B = 20, 16, 3
+    case = dict(atoms=synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64), weights=synth.dirichlet_weights(rng, R),
+                settings=synth.random_settings(rng, B, n))
+    case["freqs"] = synth.porter_thomas_freqs(rng, B, 1 << n, synth.dirichlet_weights(rng, 4), 1_000_000)
+    return case, oracle(case, born.LOSS_CE, 1e-8, tier="axis")
+
+
+def _check_n20(h, n20_sample, path, tol, atoms_checked=(0, 5, 15)):
+    case, (Lr, pr, gar, gwr) = n20_sample
+    L, p, ga, gw = _run(h, case, path)
+    assert abs(L - Lr) <= tol * abs(Lr), (L, Lr)
+    assert close(p, pr, tol), rel(p, pr)
+    for r in atoms_checked:
+        assert close(ga[r], gar[r], tol), (r, rel(ga[r], gar[r]))
+    assert close(gw, gwr, tol), rel(gw, gwr)
+
+
 @pytest.mark.parametrize("path_name", ["PATH_TILE_F16", "PATH_TILE_BF16"])
-def test_tile_path_full_size_subset(h, path_name):
-    """n=20, R=16 on four settings: the tile path against the FP32 butterfly path."""
+def test_tile_path_full_size_subset(h, n20_sample, path_name):
+    """n=20, R=16 on three settings: the tile path against the oracle."""
     from paper_2607_19577_amd import api
 
-    rng = synth.make_rng(960)
-    n, R, B = 20, 16, 4
-    atoms = torch.from_numpy(synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64)).to(DEV)
-    w = torch.from_numpy(synth.dirichlet_weights(rng, R)).to(DEV)
-    s = torch.from_numpy(synth.random_settings(rng, B, n)).to(DEV)
-    f = synth.porter_thomas_freqs_torch(961, B, 1 << n, synth.dirichlet_weights(rng, 4), 1_000_000, DEV)
-    inst = api.Instance(atoms, w, s, f)
-    ref = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8)
-    got = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=getattr(api, path_name))
-    pr, _ = api.qst_forward(h, [inst], want_probs=True)
-    pg, _ = api.qst_forward(h, [inst], want_probs=True, path=getattr(api, path_name))
-    torch.cuda.synchronize()
-    tol = TIGHT[path_name]
-    assert abs(float(got[0][0]) - float(ref[0][0])) <= tol * abs(float(ref[0][0]))
-    assert close(pg[0].cpu().numpy(), pr[0].cpu().numpy(), tol)
-    a, b = got[1][0].cpu().numpy(), ref[1][0].cpu().numpy()
-    for r in (0, 5, 15):
-        assert close(a[r], b[r], tol), (r, rel(a[r], b[r]))
-    assert close(got[2][0].cpu().numpy(), ref[2][0].cpu().numpy(), tol)
+    print("tile n=20 subset", path_name, flush=True)
+    _check_n20(h, n20_sample, getattr(api, path_name), TIGHT[path_name])
 
 
 # ---------------------------------------------------------------- FP32 butterflies with BF16 intermediates
@@ -150,21 +154,9 @@ def test_bf16_intermediates_batched_instances(h):
             assert close(g[r], gar[r], TOL_BF16X), (i, r, rel(g[r], gar[r]))
 
 
-def test_bf16_intermediates_full_size_subset(h):
-    """n=20, R=16 on four settings against the FP32 butterfly path."""
+def test_bf16_intermediates_full_size_subset(h, n20_sample):
+    """n=20, R=16 on three settings against the oracle."""
     from paper_2607_19577_amd import api
 
-    rng = synth.make_rng(990)
-    n, R, B = 20, 16, 4
-    atoms = torch.from_numpy(synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64)).to(DEV)
-    w = torch.from_numpy(synth.dirichlet_weights(rng, R)).to(DEV)
-    s = torch.from_numpy(synth.random_settings(rng, B, n)).to(DEV)
-    f = synth.porter_thomas_freqs_torch(991, B, 1 << n, synth.dirichlet_weights(rng, 4), 1_000_000, DEV)
-    inst = api.Instance(atoms, w, s, f)
-    ref = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8)
-    got = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=api.PATH_BUTTERFLY_BF16)
-    torch.cuda.synchronize()
-    assert abs(float(got[0][0]) - float(ref[0][0])) <= TOL_BF16X * abs(float(ref[0][0]))
-    a, b = got[1][0].cpu().numpy(), ref[1][0].cpu().numpy()
-    for r in (0, 5, 15):
-        assert close(a[r], b[r], TOL_BF16X), (r, rel(a[r], b[r]))
+    print("bf16 intermediates n=20 subset", flush=True)
+    _check_n20(h, n20_sample, api.PATH_BUTTERFLY_BF16, TOL_BF16X)
