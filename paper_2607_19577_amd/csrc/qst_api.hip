@@ -751,56 +751,86 @@ qst_status run_batch(qst_handle* h, const std::vector<const RunSpec*>& rs) {
 // chip (qst_onchip.hip): pass F forms p, the loss and 2^-k g per setting with the atoms
 // looped, pass A recomputes each atom's rotation per setting and sums the adjoint over a
 // slice of settings in registers.  No intermediate amplitudes cross HBM.
-bool oc_eligible(const RunSpec& r) {
+// FP32 Pauli settings with dense data and the library's own batch size: the kinds below apply.
+bool dev_table_eligible(const RunSpec& r) {
   const qst_instance& in = *r.in;
   if (resolve(r.path) != QST_PATH_BUTTERFLY_F32) return false;
-  if (in.unitaries || in.freqs_rowptr || in.settings_per_batch > 0) return false;
-  if (in.n_qubits < 11 || in.n_qubits > 14) return false;
+  return !in.unitaries && !in.freqs_rowptr && in.settings_per_batch <= 0;
+}
+
+bool oc_eligible(const RunSpec& r) {
+  const qst_instance& in = *r.in;
+  if (!dev_table_eligible(r) || in.n_qubits < 11 || in.n_qubits > 14) return false;
   // the outcome rows are read and written four values at a time
   auto a16 = [](const void* p) { return p == nullptr || aligned(p, 16); };
   return a16(in.freqs) && a16(in.probs_base) && a16(r.probs) && a16(r.grad_p) && a16(r.gneg) && a16(r.atom_grad) &&
          a16(in.atoms);
 }
 
-// QST_ONCHIP (environment, read once): 0 never, 1 for every eligible instance; unset: when
-// the atoms of a setting do not fit one low-stage work-group (R 2^n > 2^14).
+int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
+}
+
+// Experiment switches (environment, read once): QST_ONCHIP 0 never / 1 for every eligible
+// instance (default: when R 2^n > 2^14), QST_FS 0 turns the fused slices off.
 int env_onchip() {
-  static const int v = [] {
-    const char* e = std::getenv("QST_ONCHIP");
-    return e ? std::atoi(e) : -1;
-  }();
+  static const int v = env_int("QST_ONCHIP", -1);
+  return v;
+}
+int env_fs() {
+  static const int v = env_int("QST_FS", 1);
   return v;
 }
 
-bool oc_use(const RunSpec& r) {
-  if (!oc_eligible(r)) return false;
+// Kind of the device-table path an instance takes: 0 none, 1 atoms looped on chip (pass F and
+// pass A), 2 fused slices (every atom of a setting in one work-group).
+enum { TK_NONE = 0, TK_OC = 1, TK_FS = 2 };
+
+int table_kind(const RunSpec& r) {
+  if (!dev_table_eligible(r)) return TK_NONE;
+  const bool fits = ((long long)r.in->rank << r.in->n_qubits) <= 16384;
   const int e = env_onchip();
-  if (e == 0) return false;
-  if (e == 1) return true;
-  return ((long long)r.in->rank << r.in->n_qubits) > 16384;
+  if (oc_eligible(r) && (e == 1 || (e != 0 && !fits))) return TK_OC;
+  if (fits && env_fs() != 0 && aligned(r.atom_grad, 8)) return TK_FS;
+  return TK_NONE;
 }
 
-// Slicing of pass A.  An instance is cut into enough slices to give every resident work-group
-// one item when it runs alone, but no slice has fewer than QST_OC_SLICE_MIN settings
-// (environment, default 16), which bounds the partial sums written to HBM at 16 / S_min bytes
-// per (setting, atom) amplitude.  The rule depends on the instance alone, so a call with
-// several instances gives each the same bits as a call with it alone.
+// Pass-A slicing of the atoms-looped kind: enough slices to give every resident work-group one
+// item when the instance runs alone, no slice below QST_OC_SLICE_MIN settings (default 16),
+// which bounds the slice partials written to HBM at 16 / S_min bytes per (setting, atom)
+// amplitude.
 int env_oc_slice_min() {
   static const int v = [] {
-    const char* e = std::getenv("QST_OC_SLICE_MIN");
-    const int x = e ? std::atoi(e) : 0;
+    const int x = env_int("QST_OC_SLICE_MIN", 0);
     return x > 0 ? x : 16;
   }();
   return v;
 }
 
-// Values per thread of the on-chip passes: QST_OC_LOGV (environment, read once) if it names a
-// supported shape, else 2^5.
-int oc_logv(int n) {
+// Items per resident work-group of the fused slices (QST_FS_ITEMS, default 1): the settings of
+// a launch are cut into about that many slices per work-group slot, so a call of many small
+// instances writes few partial gradients and a single one still fills the device; no slice
+// has fewer than QST_FS_SLICE_MIN settings (default 4).
+int env_fs_items() {
   static const int v = [] {
-    const char* e = std::getenv("QST_OC_LOGV");
-    return e ? std::atoi(e) : 0;
+    const int x = env_int("QST_FS_ITEMS", 0);
+    return x > 0 ? x : 1;
   }();
+  return v;
+}
+int env_fs_slice_min() {
+  static const int v = [] {
+    const int x = env_int("QST_FS_SLICE_MIN", 0);
+    return x > 0 ? x : 4;
+  }();
+  return v;
+}
+
+// Values per thread of the atoms-looped passes: QST_OC_LOGV (environment, read once) if it names
+// a supported shape, else 2^5.
+int oc_logv(int n) {
+  static const int v = env_int("QST_OC_LOGV", 0);
   return qst::oc_shape_ok(n, v) ? v : 5;
 }
 
@@ -811,76 +841,113 @@ int oc_occ(qst_handle* h, int n, int logv, bool adj) {
   return it->second;
 }
 
-qst_status run_onchip(qst_handle* h, std::vector<const RunSpec*> rs, size_t* need) {
-  // Instances grouped by n (one launch of each pass per n), larger ones first.
+int fs_occ(qst_handle* h, int n, int RM, bool adj) {
+  const auto key = std::make_pair(1000 + n * 64 + RM, adj ? 1 : 0);
+  auto it = h->oc_occupancy.find(key);
+  if (it == h->oc_occupancy.end()) it = h->oc_occupancy.emplace(key, qst::fs_blocks_per_cu(n, adj, RM)).first;
+  return it->second;
+}
+
+// The device-table path: one instance table in the workspace, then per (kind, n) one launch
+// of each pass over all instances of that class, then one launch each of the slice sums,
+// the loss and weight-gradient sums and the tangent projection.
+qst_status run_table(qst_handle* h, std::vector<const RunSpec*> rs, size_t* need) {
+  // classes (kind, n) in order, larger instances first inside a class
   std::stable_sort(rs.begin(), rs.end(), [](const RunSpec* a, const RunSpec* b) {
+    const int ka = table_kind(*a), kb = table_kind(*b);
+    if (ka != kb) return ka < kb;
     if (a->in->n_qubits != b->in->n_qubits) return a->in->n_qubits > b->in->n_qubits;
     return (long long)a->in->n_settings * a->in->rank > (long long)b->in->n_settings * b->in->rank;
   });
   const int count = (int)rs.size();
+  struct Group {
+    int kind, n, logv, RM, k0, k1, itemsF, itemsA;
+    long long settings;
+  };
+  std::vector<Group> groups;
+  for (int k = 0; k < count; ++k) {
+    const int kind = table_kind(*rs[k]);
+    const int n = rs[k]->in->n_qubits;
+    if (groups.empty() || groups.back().kind != kind || groups.back().n != n)
+      groups.push_back(Group{kind, n, kind == TK_OC ? oc_logv(n) : 5, 1, k, k, 0, 0, 0});
+    Group& gr = groups.back();
+    gr.k1 = k + 1;
+    gr.RM = std::max(gr.RM, (int)rs[k]->in->rank);
+    gr.settings += rs[k]->in->n_settings;
+  }
   std::vector<qst::OcInst> tab(count);
   size_t o = al256((size_t)count * sizeof(qst::OcInst));
   std::vector<size_t> off_pc(count), off_G(count), off_P(count), off_part(count);
-  struct Group {
-    int n, logv, k0, k1, itemsF, itemsA;
-  };
-  std::vector<Group> groups;
-  int rmax = 1, sum_blocks = 0;
+  int rmax = 1, sum_blocks = 0, dec_blocks = 0;
   bool any_rows = false, any_tan = false;
-  for (int k = 0; k < count; ++k) {
-    const RunSpec& r = *rs[k];
-    const qst_instance& in = *r.in;
-    qst::OcInst& a = tab[k];
-    a = qst::OcInst{};
-    const int n = in.n_qubits, R = in.rank, B = in.n_settings;
-    const long long D = 1ll << n;
-    const int logv = oc_logv(n);
-    const int vpw = qst::oc_threads_of(n, logv) >> (n - logv);
-    if (groups.empty() || groups.back().n != n) groups.push_back(Group{n, logv, k, k, 0, 0});
-    Group& gr = groups.back();
-    gr.k1 = k + 1;
-    a.n = n;
-    a.R = R;
-    a.B = B;
-    a.eps = r.eps;
-    a.loss_kind = r.grad_p ? 2 : (int)r.loss_kind;
-    a.ntile = (R + vpw - 1) / vpw;
-    a.sF = vpw;
-    const bool fpass = r.grad_p == nullptr;  // the caller's dL/dp replaces pass F
-    const int nF = fpass ? (B + a.sF - 1) / a.sF : 0;
-    if (r.adjoint) {
-      const int resident = h->num_cu * oc_occ(h, n, logv, true);
-      const int fill = (resident + a.ntile - 1) / a.ntile;
-      const int most = std::max(1, B / env_oc_slice_min());
-      const int nA0 = std::max(1, std::min(fill, most));
-      const int sA = std::max((B + nA0 - 1) / nA0, a.sF);
-      a.sA = sA;
-      a.nA = (B + sA - 1) / sA;
-    } else {
-      a.sA = B;
-      a.nA = 0;
+  for (Group& gr : groups) {
+    const bool adj_any = rs[gr.k0]->adjoint;
+    // fused slices: settings per slice from the launch's total (about env_fs_items() per slot)
+    int fs_slice = 1;
+    if (gr.kind == TK_FS) {
+      const long long slots = (long long)h->num_cu * fs_occ(h, gr.n, gr.RM, adj_any) * env_fs_items();
+      fs_slice = (int)std::max<long long>(env_fs_slice_min(), (gr.settings + slots - 1) / slots);
     }
-    a.nslots = std::max(nF, std::max(a.nA, 1));
-    a.itemF0 = gr.itemsF;
-    gr.itemsF += nF;
-    a.itemA0 = gr.itemsA;
-    if (r.adjoint) gr.itemsA += a.nA * a.ntile;
-    a.tangent = r.adjoint && r.project_tangent ? 1 : 0;
-    rmax = std::max(rmax, R);
-    a.loss = (r.grad_p == nullptr && r.loss_kind != QST_LOSS_NONE) ? r.loss : nullptr;
-    a.wgrad = r.adjoint ? r.weight_grad : nullptr;
-    any_rows |= a.loss != nullptr || a.wgrad != nullptr;
-    any_tan |= a.tangent != 0;
-    off_pc[k] = o;
-    o = al256(o + (size_t)B * 8);
-    off_G[k] = o;
-    if (r.adjoint && fpass) o = al256(o + (size_t)B * D * 4);
-    off_P[k] = o;
-    if (r.adjoint && a.nA > 1) o = al256(o + (size_t)a.nA * R * D * 8);
-    off_part[k] = o;
-    o = al256(o + (size_t)(R + 1) * a.nslots * 8);
-    a.sumB0 = sum_blocks;
-    if (r.adjoint && a.nA > 1) sum_blocks += (int)(((long long)R * D + 1023) / 1024);
+    for (int k = gr.k0; k < gr.k1; ++k) {
+      const RunSpec& r = *rs[k];
+      const qst_instance& in = *r.in;
+      qst::OcInst& a = tab[k];
+      a = qst::OcInst{};
+      const int n = in.n_qubits, R = in.rank, B = in.n_settings;
+      const long long D = 1ll << n;
+      a.n = n;
+      a.R = R;
+      a.B = B;
+      a.eps = r.eps;
+      a.loss_kind = r.grad_p ? 2 : (int)r.loss_kind;
+      const bool fpass = gr.kind == TK_OC && r.grad_p == nullptr;  // the caller's dL/dp replaces pass F
+      int nF = 0;
+      if (gr.kind == TK_OC) {
+        const int vpw = qst::oc_threads_of(n, gr.logv) >> (n - gr.logv);
+        a.ntile = (R + vpw - 1) / vpw;
+        a.sF = vpw;
+        nF = fpass ? (B + a.sF - 1) / a.sF : 0;
+        if (r.adjoint) {
+          const int resident = h->num_cu * oc_occ(h, n, gr.logv, true);
+          const int fill = (resident + a.ntile - 1) / a.ntile;
+          const int most = std::max(1, B / env_oc_slice_min());
+          const int nA0 = std::max(1, std::min(fill, most));
+          a.sA = std::max((B + nA0 - 1) / nA0, a.sF);
+          a.nA = (B + a.sA - 1) / a.sA;
+        } else {
+          a.sA = B;
+          a.nA = 0;
+        }
+      } else {
+        a.ntile = 1;
+        a.sF = 1;
+        a.sA = fs_slice;
+        a.nA = (B + fs_slice - 1) / fs_slice;
+      }
+      a.nslots = std::max(nF, std::max(a.nA, 1));
+      a.itemF0 = gr.itemsF;
+      gr.itemsF += nF;
+      a.itemA0 = gr.itemsA;
+      if (gr.kind == TK_FS || r.adjoint) gr.itemsA += a.nA * a.ntile;
+      a.tangent = r.adjoint && r.project_tangent ? 1 : 0;
+      rmax = std::max(rmax, R);
+      a.loss = (r.grad_p == nullptr && r.loss_kind != QST_LOSS_NONE) ? r.loss : nullptr;
+      a.wgrad = r.adjoint ? r.weight_grad : nullptr;
+      any_rows |= a.loss != nullptr || a.wgrad != nullptr;
+      any_tan |= a.tangent != 0;
+      off_pc[k] = o;
+      o = al256(o + (size_t)B * 8);
+      off_G[k] = o;
+      if (r.adjoint && fpass) o = al256(o + (size_t)B * D * 4);
+      off_P[k] = o;
+      if (r.adjoint && a.nA > 1) o = al256(o + (size_t)a.nA * R * D * 8);
+      off_part[k] = o;
+      o = al256(o + (size_t)(R + 1) * a.nslots * 8);
+      a.sumB0 = sum_blocks;
+      if (r.adjoint && a.nA > 1) sum_blocks += (int)(((long long)R * D + 31) / 32);
+      a.decB0 = dec_blocks;
+      dec_blocks += (B + 255) / 256;
+    }
   }
   if (need) {
     *need = std::max(*need, o);
@@ -895,15 +962,18 @@ qst_status run_onchip(qst_handle* h, std::vector<const RunSpec*> rs, size_t* nee
     const RunSpec& r = *rs[k];
     const qst_instance& in = *r.in;
     qst::OcInst& a = tab[k];
+    const bool oc = table_kind(r) == TK_OC;
     a.atoms = in.atoms;
     a.alpha = in.weights;
     a.pc = reinterpret_cast<const uint64_t*>(ws + off_pc[k]);
+    a.pc_out = reinterpret_cast<uint64_t*>(ws + off_pc[k]);
+    a.settings = in.settings;
     a.freqs = r.grad_p ? nullptr : in.freqs;
     a.grad_p = reinterpret_cast<const float*>(r.grad_p);
     a.pbase = reinterpret_cast<const float*>(in.probs_base);
     a.probs = reinterpret_cast<float*>(r.probs);
     a.gneg = reinterpret_cast<float*>(r.gneg);
-    a.G = (r.adjoint && r.grad_p == nullptr) ? reinterpret_cast<float*>(ws + off_G[k]) : nullptr;
+    a.G = (oc && r.adjoint && r.grad_p == nullptr) ? reinterpret_cast<float*>(ws + off_G[k]) : nullptr;
     a.P = (r.adjoint && a.nA > 1) ? reinterpret_cast<float2*>(ws + off_P[k]) : nullptr;
     a.grad = r.adjoint ? reinterpret_cast<float2*>(r.atom_grad) : nullptr;
     a.part = reinterpret_cast<double*>(ws + off_part[k]);
@@ -916,11 +986,18 @@ qst_status run_onchip(qst_handle* h, std::vector<const RunSpec*> rs, size_t* nee
     for (int i = 0; i < ch.count; ++i) ch.a[i] = tab[c0 + i];
     QST_HIP(qst::launch_oc_stage(ch, dtab, s));
   }
-  for (int k = 0; k < count; ++k)
-    QST_HIP(qst::launch_decode(rs[k]->in->settings, tab[k].B, tab[k].n, reinterpret_cast<uint64_t*>(ws + off_pc[k]),
-                               h->dflag, s));
+  QST_HIP(qst::launch_oc_decode(dtab, count, dec_blocks, h->dflag, s));
   prof_end(h);
   for (const Group& gr : groups) {
+    const bool adj = rs[gr.k0]->adjoint;
+    if (gr.kind == TK_FS) {
+      const int grid =
+          (int)std::min<long long>(gr.itemsA, (long long)h->num_cu * fs_occ(h, gr.n, gr.RM, adj));
+      prof_begin(h, PK_LO);
+      QST_HIP(qst::launch_fs_pass(gr.n, adj, dtab, gr.k0, gr.k1, gr.itemsA, gr.RM, grid, s));
+      prof_end(h);
+      continue;
+    }
     if (gr.itemsF > 0) {
       const int grid = (int)std::min<long long>(gr.itemsF, (long long)h->num_cu * oc_occ(h, gr.n, gr.logv, false));
       prof_begin(h, PK_HI_FWD);
@@ -947,16 +1024,16 @@ qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* ne
   std::vector<const RunSpec*> single;
   std::vector<const RunSpec*> onchip;
   for (const RunSpec& r : specs)
-    if (oc_use(r)) onchip.push_back(&r);
+    if (table_kind(r) != TK_NONE) onchip.push_back(&r);
   if (!onchip.empty() && h->static_ws) {
-    // without allocation the on-chip buffers must fit the static scratch, else the staged path runs
+    // without allocation the table path's buffers must fit the static scratch, else the staged path runs
     size_t oc_need = 0;
-    qst_status st = run_onchip(h, onchip, &oc_need);
+    qst_status st = run_table(h, onchip, &oc_need);
     if (st != QST_OK) return st;
     if (oc_need > h->ws_bytes) onchip.clear();
   }
   if (!onchip.empty()) {
-    qst_status st = run_onchip(h, onchip, need);
+    qst_status st = run_table(h, onchip, need);
     if (st != QST_OK) return st;
   }
   for (const RunSpec& r : specs) {

@@ -209,11 +209,14 @@ struct OcInst {
   double* part;         // [(R+1)][nslots] or null
   double* loss;         // device scalar or null
   double* wgrad;        // [R] or null
+  const uint8_t* settings;  // [B][n] Pauli codes (decoded into pc_out by k_oc_decode)
+  uint64_t* pc_out;         // the same array as pc
   long long nslots;
   double eps;
   int n, R, B, loss_kind;
   int sF, sA, nA, ntile;
   int itemF0, itemA0, sumB0, tangent;
+  int decB0, pad;           // first block of this instance in the decode launch
 };
 static_assert(sizeof(OcInst) % 4 == 0, "staged as 32-bit words");
 constexpr int kOcChunk = 16;
@@ -231,7 +234,14 @@ int oc_blocks_per_cu(int n, int logv, bool adj);
 // Pass F (adj = false) or A over items [0, total) of instances [k0, k1) (all of n qubits).
 hipError_t launch_oc_pass(int n, int logv, bool adj, const OcInst* tab, int k0, int k1, int total, int grid,
                           hipStream_t st);
+// Fused slices (states with R 2^n <= 2^14): items (instance, slice) as in pass A, every atom of
+// a setting in one work-group of fs_threads(n, RM) threads (RM: the largest rank of the launch).
+hipError_t launch_fs_pass(int n, bool adj, const OcInst* tab, int k0, int k1, int total, int RM, int grid,
+                          hipStream_t st);
+int fs_blocks_per_cu(int n, bool adj, int RM);
 hipError_t launch_oc_stage(const OcChunk& c, OcInst* tab, hipStream_t st);
+// Decode the settings of every instance of the table (blocks: sum of ceil(B / 256)).
+hipError_t launch_oc_decode(const OcInst* tab, int count, int blocks, int* flag, hipStream_t st);
 // Slice sums (sum_blocks > 0), loss and weight-gradient rows (rows), tangent projection.
 hipError_t launch_oc_finish(const OcInst* tab, int count, int sum_blocks, int rmax, bool rows, bool tangent,
                             hipStream_t st);

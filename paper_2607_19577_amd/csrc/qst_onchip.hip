@@ -281,26 +281,261 @@ __global__ __launch_bounds__((oc_threads<NB, LOGV>()), (LOGV == 5 ? 2 : 4)) void
   }
 }
 
+// ------------------------------------------------------------------ fused slices (one-chunk states)
+// States whose R atoms fit one work-group together (R 2^n <= 2^14): one pass per item =
+// (instance, slice of settings) with every atom of a setting on chip at once, as in the fused
+// low stage -- rotation, the atom sum alpha_r |phi_r|^2 through an LDS table, loss terms and
+// g = dL/dp per outcome, the weight-gradient partial sums, alpha_r 2^-k g * phi through the
+// adjoint rotation -- and the adjoint summed over the slice's settings in registers: one
+// partial gradient per slice instead of one rotated vector per setting through HBM.
+// Atom r is held by threads [r 2^(n-LOGV), (r+1) 2^(n-LOGV)); the launch is sized for the
+// largest rank RM of its instances (threads of atoms beyond an instance's rank read zeros
+// and write nothing).  ADJ = false: probabilities and loss only.
+template <int NB, bool ADJ>
+__global__ __launch_bounds__(512) void k_fs(const OcInst* __restrict__ tab, int k0, int k1, int total, int RM) {
+  constexpr int LOGV = NB < 5 ? NB : 5;
+  constexpr int V = 1 << LOGV;
+  constexpr int U = 1 << NB;
+  constexpr int UPAD = U + (U >> 5);
+  constexpr int LOG_TA = NB - LOGV;
+  constexpr int TA = 1 << LOG_TA;
+  constexpr bool WL = LOG_TA <= 6;
+  using CH = Chain<NB, LOGV>;
+  constexpr int NL = CH::count();
+  constexpr int LO0 = CH::lo(0);
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int atom = tid >> LOG_TA;
+  const int tau = tid & (TA - 1);
+  // LDS: wavefront-local transposes use one plane per atom, which also holds that atom's row
+  // of the table alpha_r |phi_r|^2 (its threads write the row after their last transpose; the
+  // other atoms read it only between the two barriers around the outcome loop); the g row
+  // follows.  Work-group transposes use a real and an imaginary plane per atom; the table and
+  // the g row alias the first rows (barriers separate the uses).
+  float* planes = reinterpret_cast<float*>(smem);
+  float* re = WL ? planes + (size_t)atom * UPAD : planes + (size_t)atom * 2 * UPAD;
+  float* im = WL ? re : re + UPAD;
+  float* qb = planes;
+  float* gb = qb + (size_t)RM * UPAD;
+  const size_t plane_rows = WL ? (size_t)RM + 1 : 2 * (size_t)RM;
+  double* red = reinterpret_cast<double*>(smem + (((plane_rows * UPAD * 4) + 15) & ~(size_t)15));
+  const uint32_t pos0 = (uint32_t)lay_pos<LOGV>(tau, 0, LO0);
+  auto off0 = [](int i) { return (uint32_t)(i << LO0); };
+
+  constexpr int NP = 4;  // data values per thread fetched ahead of the rotation
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+#pragma clang fp contract(off)
+    const int k = oc_find(k0, k1, item, [&](int kk) { return tab[kk].itemA0; });
+    const OcInst& a = tab[k];
+    const int j = item - a.itemA0;
+    const int s_beg = j * a.sA;
+    const int s_end = min(a.B, s_beg + a.sA);
+    const int R = a.R;
+    const bool active = atom < R;
+    const long long D = 1ll << NB;
+    const float al = active ? (float)a.alpha[atom] : 0.0f;
+    const float inv_b = (float)(1.0 / (double)a.B);
+    const float eps_f = (float)a.eps;
+    const uint32_t vo0 = pos0 * 8u;
+    const bool gen = a.grad_p != nullptr;
+    const bool row_data = gen || a.loss_kind != 2;
+    const float* dsrc = gen ? a.grad_p : a.freqs;
+    // the atom is read again for every setting (from L2); atoms beyond the rank read zeros
+    const rsrc_t rs = make_rsrc(a.atoms, (uint32_t)((long long)R * D * 8));
+    const uint32_t abase = (uint32_t)((long long)(active ? atom : R) * D * 8);
+    float ax[V], ay[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) ax[i] = ay[i] = 0.0f;
+    double loss_acc = 0.0, h_acc = 0.0;
+    for (int b = s_beg; b < s_end; ++b) {
+      const uint64_t pc = uniform_u64(a.pc[b]);
+      const uint32_t ym = ymask_of(pc, NB);
+      const float s2 = (float)ldexp(1.0, -nonz_count(pc, NB));
+      const long long row = (long long)b * D;
+      // this thread's outcomes are u = tid + jj * nthr; the first NP data values are fetched
+      // before the rotation, so their loads overlap it, the rest in groups of NP
+      float dv[NP];
+#pragma unroll
+      for (int jj = 0; jj < NP; ++jj) {
+        const int u = tid + jj * nthr;
+        dv[jj] = (row_data && u < U) ? dsrc[row + u] : 0.0f;
+      }
+      float x[V], y[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) bload2(x[i], y[i], rs, vo0 + abase, off0(i) * 8u);
+      apply_phase<false, LOGV>(x, y, pos0, ym, off0);
+      fwd_chain<0, CH, WL, false, LOGV>(x, y, re, im, tau, pc, nullptr);
+      float* qrow = qb + (size_t)atom * UPAD + pad_base<LOGV, 0>(tau);
+#pragma unroll
+      for (int i = 0; i < V; ++i) qrow[pad_off<0>(i)] = al * fma(x[i], x[i], y[i] * y[i]);
+      __syncthreads();
+      for (int j0 = 0; tid + j0 * nthr < U; j0 += NP) {
+        if (j0 > 0) {
+#pragma unroll
+          for (int jj = 0; jj < NP; ++jj) {
+            const int u = tid + (j0 + jj) * nthr;
+            dv[jj] = (row_data && u < U) ? dsrc[row + u] : 0.0f;
+          }
+        }
+#pragma unroll
+        for (int jj = 0; jj < NP; ++jj) {
+        const int u = tid + (j0 + jj) * nthr;
+        if (u >= U) continue;
+        float pv = 0.0f;
+        for (int r = 0; r < R; ++r) pv += qb[(size_t)r * UPAD + pad32(u)];
+        pv *= s2;
+        if (a.pbase != nullptr) pv += a.pbase[row + u];
+        if (a.probs != nullptr) a.probs[row + u] = pv;
+        float g = 0.0f;
+        const float d = dv[jj];
+        if (gen) {
+          g = d;
+        } else if (a.loss_kind == 0) {
+          if (d > 0.0f) {
+            const float fb = d * inv_b;
+            const float piv = fmaf(pv, inv_b, eps_f);
+            loss_acc -= (double)(fb * (__builtin_amdgcn_logf(piv) * 0.693147180559945309f));
+            g = -(fb * inv_b) * __builtin_amdgcn_rcpf(piv);
+          }
+        } else if (a.loss_kind == 1) {
+          const float rr = (pv - d) * inv_b;
+          loss_acc += (double)(0.5f * rr * rr);
+          g = rr * inv_b;
+        }
+        if (a.gneg != nullptr) a.gneg[row + u] = -g;
+        if (ADJ) gb[pad32(u)] = g * s2;
+        }
+      }
+      __syncthreads();
+      if constexpr (ADJ) {
+        float hl = 0.0f;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          const float gv = gb[pad_base<LOGV, 0>(tau) + pad_off<0>(i)];
+          hl = fma(gv, fma(x[i], x[i], y[i] * y[i]), hl);
+          const float sc = al * gv;
+          x[i] *= sc;
+          y[i] *= sc;
+        }
+        h_acc += (double)hl;
+        if constexpr (!WL) __syncthreads();  // every thread has read g before the planes are reused
+        adj_chain<NL - 1, CH, WL, false, LOGV>(x, y, re, im, tau, pc, nullptr);
+        apply_phase<true, LOGV>(x, y, pos0, ym, off0);
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+          ax[i] += x[i];
+          ay[i] += y[i];
+        }
+      }
+      if constexpr (!WL) __syncthreads();  // the table and g rows alias the planes of the next setting
+    }
+    if constexpr (ADJ) {
+      if (active) {
+        float2* out = a.nA == 1 ? a.grad : a.P + (long long)j * R * D;
+        const rsrc_t ro = make_rsrc(out, (uint32_t)((long long)R * D * 8));
+#pragma unroll
+        for (int i = 0; i < V; ++i) bstore2(ax[i], ay[i], ro, vo0 + abase, off0(i) * 8u);
+      }
+    }
+    // Partials of this item (slot j): loss over the work-group, h_r over atom r's threads.
+    if (a.part != nullptr) {
+      if constexpr (ADJ) {
+        red[tid] = h_acc;
+        __syncthreads();
+        for (int st = TA >> 1; st > 0; st >>= 1) {
+          if (tau < st) red[tid] += red[tid + st];
+          __syncthreads();
+        }
+        if (tau == 0 && active) a.part[(long long)(1 + atom) * a.nslots + j] = red[tid];
+        __syncthreads();
+      }
+      red[tid] = loss_acc;
+      __syncthreads();
+      int np2 = 1;
+      while (np2 < nthr) np2 <<= 1;
+      for (int st = np2 >> 1; st > 0; st >>= 1) {
+        if (tid < st && tid + st < nthr) red[tid] += red[tid + st];
+        __syncthreads();
+      }
+      if (tid == 0) a.part[j] = red[0];
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------------------------ slice sums, reductions, tangent
-// grad[k][e] = sum over slices j of P[k][j][e] in increasing j (instances with nA > 1); blocks
-// [sumB0, sumB0 + ceil(R D / 1024)) of the launch belong to instance k.
-__global__ __launch_bounds__(256) void k_oc_sum(const OcInst* __restrict__ tab, int count) {
+// grad[k][e] = sum over slices j of P[k][j][e] (instances with nA > 1).  A block takes 32
+// consecutive elements; for each, eight threads sum the slices j = t, t + 8, ... in increasing
+// order (independent loads, unrolled by four), and the eight sums are added in a fixed tree.
+// Blocks [sumB0, sumB0 + ceil(R D / 32)) of the launch belong to instance k.
+constexpr int kOcSumCols = 32;
+constexpr int kOcSumThreads = 8;
+__global__ __launch_bounds__(kOcSumCols * kOcSumThreads) void k_oc_sum(const OcInst* __restrict__ tab, int count) {
+  __shared__ float2 part[kOcSumThreads][kOcSumCols];
   const int k = oc_find(0, count, (int)blockIdx.x, [&](int kk) { return tab[kk].sumB0; });
   const OcInst& a = tab[k];
   if (a.nA <= 1) return;
   const long long RD = (long long)a.R << a.n;
-  const long long e0 = ((long long)blockIdx.x - a.sumB0) * 1024 + threadIdx.x;
-  for (int q = 0; q < 4; ++q) {
-    const long long e = e0 + q * 256;
-    if (e >= RD) break;
-    float sx = 0.0f, sy = 0.0f;
-    for (int jj = 0; jj < a.nA; ++jj) {
-      const float2 v = a.P[(long long)jj * RD + e];
+  const int col = threadIdx.x % kOcSumCols, t = threadIdx.x / kOcSumCols;
+  const long long e = ((long long)blockIdx.x - a.sumB0) * kOcSumCols + col;
+  float sx = 0.0f, sy = 0.0f;
+  if (e < RD) {
+    const float2* P = a.P + e;
+    int jj = t;
+    for (; jj + 3 * kOcSumThreads < a.nA; jj += 4 * kOcSumThreads) {
+      const float2 v0 = P[(long long)jj * RD], v1 = P[(long long)(jj + kOcSumThreads) * RD];
+      const float2 v2 = P[(long long)(jj + 2 * kOcSumThreads) * RD], v3 = P[(long long)(jj + 3 * kOcSumThreads) * RD];
+      sx += v0.x;
+      sy += v0.y;
+      sx += v1.x;
+      sy += v1.y;
+      sx += v2.x;
+      sy += v2.y;
+      sx += v3.x;
+      sy += v3.y;
+    }
+    for (; jj < a.nA; jj += kOcSumThreads) {
+      const float2 v = P[(long long)jj * RD];
       sx += v.x;
       sy += v.y;
     }
-    a.grad[e] = make_float2(sx, sy);
   }
+  part[t][col] = make_float2(sx, sy);
+  __syncthreads();
+  if (t == 0 && e < RD) {
+    auto add = [](float2 u, float2 v) { return make_float2(u.x + v.x, u.y + v.y); };
+    const float2 p01 = add(part[0][col], part[1][col]), p23 = add(part[2][col], part[3][col]);
+    const float2 p45 = add(part[4][col], part[5][col]), p67 = add(part[6][col], part[7][col]);
+    a.grad[e] = add(add(p01, p23), add(p45, p67));
+  }
+}
+
+// Pauli codes of every instance's settings, one thread per setting: 2 bits per qubit, qubit j
+// at index bit n-1-j (codes above 2 are taken as Z and raise bit 0 of the flag).  Blocks
+// [decB0, decB0 + ceil(B / 256)) belong to instance k.
+__global__ __launch_bounds__(256) void k_oc_decode(const OcInst* __restrict__ tab, int count, int* __restrict__ flag) {
+  const int k = oc_find(0, count, (int)blockIdx.x, [&](int kk) { return tab[kk].decB0; });
+  const OcInst& a = tab[k];
+  const int b = ((int)blockIdx.x - a.decB0) * 256 + (int)threadIdx.x;
+  if (b >= a.B) return;
+  uint64_t v = 0;
+  int bad = 0;
+  for (int j = 0; j < a.n; ++j) {
+    uint32_t c = a.settings[(size_t)b * a.n + j];
+    if (c > 2u) {
+      bad = 1;
+      c = 2u;
+    }
+    v |= (uint64_t)c << (2 * (a.n - 1 - j));
+  }
+  a.pc_out[b] = v;
+  if (bad) atomicOr(flag, 1);
+}
+
+hipError_t launch_oc_decode(const OcInst* tab, int count, int blocks, int* flag, hipStream_t st) {
+  if (blocks > 0) k_oc_decode<<<blocks, 256, 0, st>>>(tab, count, flag);
+  return hipGetLastError();
 }
 
 __device__ __forceinline__ double oc_block_sum(double v, double* red) {
@@ -445,6 +680,65 @@ int oc_blocks_per_cu(int n, int logv, bool adj) {
   return 1;
 }
 
+size_t fs_lds_bytes(int n, int RM) {
+  const int logv = n < 5 ? n : 5;
+  const bool wl = n - logv <= 6;
+  const size_t U = (size_t)1 << n;
+  const size_t rows = wl ? (size_t)RM + 1 : 2 * (size_t)RM;
+  const size_t nthr = (size_t)RM << (n - logv);
+  return ((rows * (U + (U >> 5)) * 4 + 15) & ~(size_t)15) + nthr * sizeof(double);
+}
+
+int fs_threads(int n, int RM) { return RM << (n - (n < 5 ? n : 5)); }
+
+template <int NB>
+static hipError_t fs_launch(bool adj, const OcInst* tab, int k0, int k1, int total, int RM, int grid, hipStream_t st) {
+  const size_t lds = fs_lds_bytes(NB, RM);
+  const void* fn = adj ? reinterpret_cast<const void*>(&k_fs<NB, true>) : reinterpret_cast<const void*>(&k_fs<NB, false>);
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (adj)
+    k_fs<NB, true><<<grid, fs_threads(NB, RM), lds, st>>>(tab, k0, k1, total, RM);
+  else
+    k_fs<NB, false><<<grid, fs_threads(NB, RM), lds, st>>>(tab, k0, k1, total, RM);
+  return hipGetLastError();
+}
+
+template <int NB>
+static int fs_occ(bool adj, int RM) {
+  const size_t lds = fs_lds_bytes(NB, RM);
+  const void* fn = adj ? reinterpret_cast<const void*>(&k_fs<NB, true>) : reinterpret_cast<const void*>(&k_fs<NB, false>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 1;
+  int blocks = 0;
+  const hipError_t e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fs<NB, true>, fs_threads(NB, RM), lds)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_fs<NB, false>, fs_threads(NB, RM), lds);
+  return (e == hipSuccess && blocks > 0) ? blocks : 1;
+}
+
+#define QST_FS_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+
+hipError_t launch_fs_pass(int n, bool adj, const OcInst* tab, int k0, int k1, int total, int RM, int grid,
+                          hipStream_t st) {
+  if (((long long)RM << n) > 16384) return hipErrorInvalidValue;
+  switch (n) {
+#define QST_C(N) \
+  case N: return fs_launch<N>(adj, tab, k0, k1, total, RM, grid, st);
+    QST_FS_CASES(QST_C)
+#undef QST_C
+  }
+  return hipErrorInvalidValue;
+}
+
+int fs_blocks_per_cu(int n, bool adj, int RM) {
+  switch (n) {
+#define QST_C(N) \
+  case N: return fs_occ<N>(adj, RM);
+    QST_FS_CASES(QST_C)
+#undef QST_C
+  }
+  return 1;
+}
+
 hipError_t launch_oc_stage(const OcChunk& c, OcInst* tab, hipStream_t st) {
   k_oc_stage<<<1, 256, 0, st>>>(c, tab);
   return hipGetLastError();
@@ -452,7 +746,7 @@ hipError_t launch_oc_stage(const OcChunk& c, OcInst* tab, hipStream_t st) {
 
 hipError_t launch_oc_finish(const OcInst* tab, int count, int sum_blocks, int rmax, bool rows, bool tangent,
                             hipStream_t st) {
-  if (sum_blocks > 0) k_oc_sum<<<sum_blocks, 256, 0, st>>>(tab, count);
+  if (sum_blocks > 0) k_oc_sum<<<sum_blocks, kOcSumCols * kOcSumThreads, 0, st>>>(tab, count);
   if (rows) k_oc_rowsum<<<dim3(count, rmax + 1), 256, 0, st>>>(tab);
   if (tangent) k_oc_tangent<<<dim3(count, rmax), 256, 0, st>>>(tab);
   return hipGetLastError();

@@ -1,11 +1,12 @@
-"""GPU parity of multi-instance calls: batches of small instances of uneven n, R and B
-run as one launch per step (grouped by n, at most 16 instances per launch), mixed
-with instances that take the staged path one by one.
+"""GPU parity of multi-instance calls: instances of uneven n, R and B run as one launch
+of each pass per class of equal n (any number of instances, from one instance table in
+device memory), mixed with instances that take the staged path one by one.
 
 * every instance of a batched call matches the FP64 oracle (1e-5, FP32 path);
-* a batched call matches one-at-a-time calls: probabilities and atom gradients bit
-  for bit, loss and weight gradient to 1e-12 (FP64 sums of per-work-group partials
-  whose grouping depends on the launch grid);
+* a batched call matches one-at-a-time calls: probabilities bit for bit, loss and weight
+  gradient to 1e-12 (FP64 sums of per-item partials), atom gradients to 1e-6 norm-wise
+  (FP32 sums over slices of settings whose size follows the launch's total work; 1e-5 after
+  the tangent projection);
 * the uneven 64-instance workload (n in 6..12, R in 1..8, B in 50..500) against
   one-at-a-time calls, and captured in a graph and replayed.
 """
@@ -70,7 +71,7 @@ def test_batched_call_matches_single_calls(h, uneven):
         p1, l1f = api.qst_forward(h, [inst], want_probs=True, loss=api.LOSS_LS, eps=0.0)
         l1, a1, w1 = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8)
         assert torch.equal(probs[i], p1[0]), i
-        assert torch.equal(ag[i], a1[0]), i
+        assert rel(ag[i].cpu().numpy(), a1[0].cpu().numpy()) <= 1e-6, i
         assert abs(float(lf[i]) - float(l1f[0])) <= 1e-12 * abs(float(l1f[0])), i
         assert abs(float(lt[i]) - float(l1[0])) <= 1e-12 * abs(float(l1[0])), i
         torch.testing.assert_close(wg[i], w1[0], rtol=1e-12, atol=1e-300)
@@ -87,7 +88,7 @@ def test_batched_generic_sensitivity(h, uneven):
     _, ag, wg = api.qst_backward(h, insts, grad_p=gps)
     for i, inst in enumerate(insts):
         _, a1, w1 = api.qst_backward(h, [inst], grad_p=[gps[i]])
-        assert torch.equal(ag[i], a1[0]), i
+        assert rel(ag[i].cpu().numpy(), a1[0].cpu().numpy()) <= 1e-6, i
         torch.testing.assert_close(wg[i], w1[0], rtol=1e-12, atol=1e-300)
 
 
@@ -115,8 +116,10 @@ def test_uneven64_batched_matches_single(h, uneven64):
         l1, a1, w1 = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, project_tangent=True)
         assert abs(float(lt[i]) - float(l1[0])) <= 1e-12 * abs(float(l1[0])), i
         torch.testing.assert_close(wg[i], w1[0], rtol=1e-12, atol=1e-300)
-        # the tangent projection's inner products are summed in a different grouping
-        torch.testing.assert_close(ag[i], a1[0], rtol=1e-6, atol=1e-6 * float(a1[0].abs().max()))
+        # the settings are summed in slices whose size follows the launch's total work; after the
+        # tangent projection removes most of each gradient, the FP32 bar (1e-5) applies
+        for r in range(ag[i].shape[0]):
+            assert rel(ag[i][r].cpu().numpy(), a1[0][r].cpu().numpy()) <= 1e-5, (i, r)
 
 
 def test_uneven64_graph_replay(h, uneven64):

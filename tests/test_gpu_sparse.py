@@ -73,6 +73,9 @@ def test_sparse_equals_dense_storage(h, n):
 
     case = make_case(1730 + n, n, 3, 5, shots=300)
     dense, sparse = to_device(case, DEV), _sparse_inst(case)
+    # the same kernels for both storages: an explicit batch size keeps the dense instance on the
+    # staged (or one-chunk fused) path that sparse data takes
+    dense.settings_per_batch = sparse.settings_per_batch = 5
     a = api.qst_backward(h, [dense], loss=api.LOSS_CE, eps=1e-8)
     b = api.qst_backward(h, [sparse], loss=api.LOSS_CE, eps=1e-8)
     torch.cuda.synchronize()
