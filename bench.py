@@ -274,8 +274,9 @@ def onchip_extra(api, h, dev, seed: int, steps: int = 20, warmup: int = 3):
 
 def uneven_batch_extra(api, h, dev, seed: int, reps: int = 5):
     """64 independent instances, n in 6..12, R in 1..8, B in 50..500 (fused CE backward with the
-    tangent projection): one call (batched launches), the same call replayed from a graph, and
-    64 one-instance calls.  Median wall time of `reps` runs each."""
+    tangent projection), planned with the autotuner: one call (one launch of each pass per class
+    of equal n), the same call replayed from a graph, and 64 one-instance calls.  Median wall
+    time of `reps` runs each."""
     import torch
 
     rng = synth.make_rng(seed)
@@ -291,7 +292,9 @@ def uneven_batch_extra(api, h, dev, seed: int, reps: int = 5):
                                             10_000, dev)
         insts.append(api.Instance(atoms, w, st, f))
         amps += B * R * (1 << n)
-    api.qst_plan(h, insts)
+    # the autotuner times the call's routing (which instances run atoms-looped on chip or as fused
+    # slices) and keeps the fastest for calls with these shapes
+    api.qst_plan(h, insts, autotune=True)
 
     def timed(fn):
         ts = []

@@ -171,12 +171,40 @@ const char* qst_status_string(qst_status s);
 /* Message of the last error on this handle ("" if none); valid until the next call. */
 const char* qst_last_error(const qst_handle* h);
 
-/* Reserve workspace and choose the setting-batch size for these shapes; when
- * `autotune` is non-zero the candidates are timed on the handle's stream (this
- * synchronises).  Later calls with shapes that fit the reservation allocate
- * nothing, so they may be captured into a HIP graph.  Optional: the compute
- * calls plan implicitly. */
+/* Reserve workspace for these shapes; when `autotune` is non-zero, implementation choices are
+ * timed on the handle's stream (this synchronises): for one instance, the kernels, batch size
+ * and tile bits of its shape (qst_choice below); for several, the routing of the whole call
+ * (which instances run atoms-looped or as fused slices), kept for calls with the same shapes.
+ * Later calls with shapes that fit the reservation allocate nothing, so they may be captured
+ * into a HIP graph.  Optional: the compute calls plan implicitly. */
 qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_path path, int autotune);
+
+/* Implementation choices for one instance shape (n_qubits, rank, n_settings rounded up to a
+ * power of two, path): which kernels run it and with which batch and tile sizes.  qst_plan with
+ * autotune times the candidates that apply to the shape on a slice of at most 256 of its
+ * settings and keeps the fastest, in the handle and in a process-wide cache keyed by the GPU
+ * architecture and the shape (a later handle on the same architecture reuses it without timing).
+ * Every field 0 (-1 for kind) means the library default.  Different choices give results equal
+ * to rounding (the sums over settings and layouts are associated differently); one choice always
+ * gives the same bits. */
+typedef struct {
+  int32_t kind;                  /* -1 default, 0 staged / one-chunk kernels (setting batches through
+                                    HBM), 1 atoms looped on chip (n = 11..14), 2 fused slices (all
+                                    atoms of a setting in one work-group: R 2^n <= 2^14)      */
+  int32_t settings_per_batch;    /* kind 0: settings per batch of intermediates               */
+  int32_t tile_bits_fwd;         /* kind 0 with high bits: tile bits of the forward tile stage */
+  int32_t tile_bits_adj;         /* ... and of the adjoint tile stage (11..14, shape permitting) */
+  int32_t values_per_thread_log2;/* kind 1: 4 (n = 13, 14) or 5                               */
+  int32_t tuned;                 /* out: 1 when the choice comes from qst_plan's timing        */
+  double best_ms;                /* out: time of the chosen candidate on the timing slice      */
+  double default_ms;             /* out: time of the library default on the same slice         */
+} qst_choice;
+
+/* Read (set = 0) or pin (set = 1) the choice for the shape of `inst` on `path`.  Reading a shape
+ * without a choice returns the defaults (kind -1, tuned 0).  A pinned choice is used by every
+ * later call on this handle with that shape; a kind that does not apply to a call's instance
+ * (e.g. unaligned arrays, general settings) falls back to the default for that call. */
+qst_status qst_plan_choice(qst_handle* h, const qst_instance* inst, qst_path path, int set, qst_choice* choice);
 
 /* Forward map (eq. atomic-born-map) for n_inst instances.
  *   probs[i]  [B][D] per-setting probabilities (float32; float64 for the F64 path),

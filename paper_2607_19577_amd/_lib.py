@@ -26,7 +26,7 @@ LOSS_CE, LOSS_LS, LOSS_NONE = 0, 1, 2
 EXPORTS = (
     "qst_create", "qst_destroy", "qst_set_stream", "qst_status_string", "qst_last_error", "qst_plan",
     "qst_forward", "qst_backward", "qst_backward_static", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor", "qst_solve",
-    "qst_state_error", "qst_build_info", "qst_profile_enable", "qst_profile_read",
+    "qst_state_error", "qst_build_info", "qst_profile_enable", "qst_profile_read", "qst_plan_choice",
 )
 
 
@@ -65,6 +65,19 @@ class QstSolveParams(ctypes.Structure):
         ("tau", ctypes.c_double),
         ("tau_acc", ctypes.c_double),
         ("oracle_budget", ctypes.c_int64),
+    ]
+
+
+class QstChoice(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("settings_per_batch", ctypes.c_int32),
+        ("tile_bits_fwd", ctypes.c_int32),
+        ("tile_bits_adj", ctypes.c_int32),
+        ("values_per_thread_log2", ctypes.c_int32),
+        ("tuned", ctypes.c_int32),
+        ("best_ms", ctypes.c_double),
+        ("default_ms", ctypes.c_double),
     ]
 
 
@@ -109,6 +122,7 @@ def load() -> ctypes.CDLL:
     lib.qst_solve.argtypes = [vp, P(QstInstance), P(QstSolveParams), vp, ctypes.c_int, vp, vp, P(i32), vp, vp,
                               ctypes.c_int]
     lib.qst_state_error.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, P(dbl), ctypes.c_int]
+    lib.qst_plan_choice.argtypes = [vp, P(QstInstance), ctypes.c_int, ctypes.c_int, P(QstChoice)]
     lib.qst_profile_enable.argtypes = [vp, ctypes.c_int]
     lib.qst_profile_read.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), P(dbl), ctypes.c_int]
     for name in EXPORTS:

@@ -14,12 +14,12 @@ import torch
 
 from . import _lib
 from ._lib import (LOSS_CE, LOSS_LS, LOSS_NONE, PATH_AUTO, PATH_BUTTERFLY_BF16, PATH_BUTTERFLY_F32,
-                   PATH_BUTTERFLY_F64, PATH_PLAIN_F32, PATH_TILE_BF16, PATH_TILE_F16, QSTError, QstInstance,
-                   QstSolveParams)
+                   PATH_BUTTERFLY_F64, PATH_PLAIN_F32, PATH_TILE_BF16, PATH_TILE_F16, QSTError, QstChoice,
+                   QstInstance, QstSolveParams)
 
 __all__ = [
     "Handle", "Instance", "qst_forward", "qst_backward", "qst_backward_static", "qst_atom_trial", "qst_reweight_simplex", "qst_refactor",
-    "qst_plan", "qst_solve", "qst_state_error", "SolveParams",
+    "qst_plan", "qst_plan_choice", "qst_solve", "qst_state_error", "SolveParams",
     "LOSS_CE", "LOSS_LS", "LOSS_NONE", "PATH_AUTO", "PATH_BUTTERFLY_F32", "PATH_BUTTERFLY_F64", "PATH_PLAIN_F32",
     "PATH_TILE_F16", "PATH_TILE_BF16", "PATH_BUTTERFLY_BF16", "QSTError",
 ]
@@ -169,6 +169,24 @@ def _real_of(path: int):
 def qst_plan(h: Handle, insts: Sequence[Instance], path: int = PATH_AUTO, autotune: bool = False) -> None:
     arr = _structs(insts, path)
     _lib.check(h.lib.qst_plan(h.h, arr, len(insts), path, int(autotune)), h.h)
+
+
+CHOICE_FIELDS = ("kind", "settings_per_batch", "tile_bits_fwd", "tile_bits_adj", "values_per_thread_log2", "tuned",
+                 "best_ms", "default_ms")
+
+
+def qst_plan_choice(h: Handle, inst: Instance, path: int = PATH_AUTO, set_to: Optional[dict] = None) -> dict:
+    """The implementation choice for the shape of ``inst`` (a dict of ``CHOICE_FIELDS``); with
+    ``set_to`` the given fields are pinned first (missing ones take the defaults)."""
+    arr = _structs([inst], path)
+    c = QstChoice()
+    c.kind = -1
+    if set_to is not None:
+        for k, v in set_to.items():
+            setattr(c, k, v)
+        _lib.check(h.lib.qst_plan_choice(h.h, arr, path, 1, ctypes.byref(c)), h.h)
+    _lib.check(h.lib.qst_plan_choice(h.h, arr, path, 0, ctypes.byref(c)), h.h)
+    return {k: getattr(c, k) for k in CHOICE_FIELDS}
 
 
 def qst_forward(h: Handle, insts: Sequence[Instance], want_probs: bool = True, loss: int = LOSS_NONE,

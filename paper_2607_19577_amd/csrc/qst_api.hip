@@ -39,7 +39,12 @@ struct qst_handle {
   int* hflag = nullptr;  // pinned host copy
   hipEvent_t flag_ev = nullptr;
   bool flag_pending = false;
-  std::map<std::tuple<int, int, int, int>, int> tuned_S;  // (n, R, B, path) -> settings per batch
+  // implementation choices per shape (n, R, B rounded up to a power of two, path) and routing
+  // policies per call signature (qst_plan with autotune, qst_plan_choice)
+  std::map<std::tuple<int, int, int, int>, qst_choice> choices;
+  std::map<uint64_t, std::pair<int, int>> policies;  // signature -> (onchip mode, fused slices)
+  std::pair<int, int> cur_policy{-1, -1};            // policy of the call being run
+  std::string arch;
   std::map<std::tuple<int, int, int, int>, int> occupancy;  // (n_lo, n_hi > 0, R, elem) -> low-stage WGs per CU
   std::map<std::pair<int, int>, int> oc_occupancy;           // (n, adjoint) -> on-chip pass WGs per CU
   // stage timing
@@ -159,6 +164,22 @@ int env_tile_bits(int which) {
   return v[which];
 }
 
+int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x && p < (1 << 30)) p <<= 1;
+  return p;
+}
+
+std::tuple<int, int, int, int> shape_key(int n, int R, int B, qst_path path) {
+  return std::make_tuple(n, R, pow2_at_least(B), (int)path);
+}
+
+// The handle's choice for a shape, or null.
+const qst_choice* find_choice(const qst_handle* h, int n, int R, int B, qst_path path) {
+  auto it = h->choices.find(shape_key(n, R, B, path));
+  return it == h->choices.end() ? nullptr : &it->second;
+}
+
 // Geometry of the staged path for (n, R, B).
 qst_status make_geometry(qst_handle* h, int n, int R, int B, qst_path path, Geometry& g) {
   const int elem = elem_of(path);
@@ -195,6 +216,10 @@ qst_status make_geometry(qst_handle* h, int n, int R, int B, qst_path path, Geom
     };
     g.t = std::min(n, env_tile_bits(0) > 0 ? env_tile_bits(0) : 14);
     g.t_adj = std::min(n, env_tile_bits(1) > 0 ? env_tile_bits(1) : 14);
+    if (const qst_choice* c = find_choice(h, n, R, B, path)) {
+      if (c->tile_bits_fwd > 0 && tile_ok(c->tile_bits_fwd)) g.t = c->tile_bits_fwd;
+      if (c->tile_bits_adj > 0 && tile_ok(c->tile_bits_adj)) g.t_adj = c->tile_bits_adj;
+    }
     if (!tile_ok(g.t) || !tile_ok(g.t_adj))
       return set_err(h, QST_ERR_UNSUPPORTED,
                      "n=" + std::to_string(n) + ", R=" + std::to_string(R) + " is outside the tile-stage shapes");
@@ -374,8 +399,8 @@ void mark(Geometry& g, const qst_instance& in) {
 int batch_size(const qst_handle* h, const Geometry& g, const qst_instance& in, qst_path path, int S_override) {
   if (S_override > 0) return std::min(S_override, g.B);
   if (in.settings_per_batch > 0) return std::min((int)in.settings_per_batch, g.B);
-  auto it = h->tuned_S.find(std::make_tuple(g.n, g.R, g.B, (int)path));
-  if (it != h->tuned_S.end()) return std::min(it->second, g.B);
+  if (const qst_choice* c = find_choice(h, g.n, g.R, g.B, path))
+    if (c->settings_per_batch > 0) return std::min((int)c->settings_per_batch, g.B);
   return default_S(g);
 }
 
@@ -787,12 +812,22 @@ int env_fs() {
 // pass A), 2 fused slices (every atom of a setting in one work-group).
 enum { TK_NONE = 0, TK_OC = 1, TK_FS = 2 };
 
-int table_kind(const RunSpec& r) {
+// Order of precedence: the shape's choice (qst_plan_choice, autotune), the routing policy of
+// the call (autotune of a multi-instance call), the environment switches, the default rule.
+int table_kind(const qst_handle* h, const RunSpec& r) {
   if (!dev_table_eligible(r)) return TK_NONE;
-  const bool fits = ((long long)r.in->rank << r.in->n_qubits) <= 16384;
-  const int e = env_onchip();
+  const qst_instance& in = *r.in;
+  const bool fits = ((long long)in.rank << in.n_qubits) <= 16384;
+  const bool fs_ok = fits && aligned(r.atom_grad, 8);
+  if (const qst_choice* c = find_choice(h, in.n_qubits, in.rank, in.n_settings, resolve(r.path))) {
+    if (c->kind == 0) return TK_NONE;
+    if (c->kind == 1 && oc_eligible(r)) return TK_OC;
+    if (c->kind == 2 && fs_ok) return TK_FS;
+  }
+  const int e = h->cur_policy.first >= 0 ? h->cur_policy.first : env_onchip();
+  const int f = h->cur_policy.second >= 0 ? h->cur_policy.second : env_fs();
   if (oc_eligible(r) && (e == 1 || (e != 0 && !fits))) return TK_OC;
-  if (fits && env_fs() != 0 && aligned(r.atom_grad, 8)) return TK_FS;
+  if (fs_ok && f != 0) return TK_FS;
   return TK_NONE;
 }
 
@@ -829,8 +864,11 @@ int env_fs_slice_min() {
 
 // Values per thread of the atoms-looped passes: QST_OC_LOGV (environment, read once) if it names
 // a supported shape, else 2^5.
-int oc_logv(int n) {
+int oc_logv(const qst_handle* h, const RunSpec& r) {
   static const int v = env_int("QST_OC_LOGV", 0);
+  const int n = r.in->n_qubits;
+  if (const qst_choice* c = find_choice(h, n, r.in->rank, r.in->n_settings, resolve(r.path)))
+    if (qst::oc_shape_ok(n, c->values_per_thread_log2)) return c->values_per_thread_log2;
   return qst::oc_shape_ok(n, v) ? v : 5;
 }
 
@@ -853,10 +891,12 @@ int fs_occ(qst_handle* h, int n, int RM, bool adj) {
 // the loss and weight-gradient sums and the tangent projection.
 qst_status run_table(qst_handle* h, std::vector<const RunSpec*> rs, size_t* need) {
   // classes (kind, n) in order, larger instances first inside a class
-  std::stable_sort(rs.begin(), rs.end(), [](const RunSpec* a, const RunSpec* b) {
-    const int ka = table_kind(*a), kb = table_kind(*b);
+  std::stable_sort(rs.begin(), rs.end(), [h](const RunSpec* a, const RunSpec* b) {
+    const int ka = table_kind(h, *a), kb = table_kind(h, *b);
     if (ka != kb) return ka < kb;
     if (a->in->n_qubits != b->in->n_qubits) return a->in->n_qubits > b->in->n_qubits;
+    const int la = ka == TK_OC ? oc_logv(h, *a) : 0, lb = kb == TK_OC ? oc_logv(h, *b) : 0;
+    if (la != lb) return la < lb;
     return (long long)a->in->n_settings * a->in->rank > (long long)b->in->n_settings * b->in->rank;
   });
   const int count = (int)rs.size();
@@ -866,10 +906,11 @@ qst_status run_table(qst_handle* h, std::vector<const RunSpec*> rs, size_t* need
   };
   std::vector<Group> groups;
   for (int k = 0; k < count; ++k) {
-    const int kind = table_kind(*rs[k]);
+    const int kind = table_kind(h, *rs[k]);
     const int n = rs[k]->in->n_qubits;
-    if (groups.empty() || groups.back().kind != kind || groups.back().n != n)
-      groups.push_back(Group{kind, n, kind == TK_OC ? oc_logv(n) : 5, 1, k, k, 0, 0, 0});
+    const int logv = kind == TK_OC ? oc_logv(h, *rs[k]) : 5;
+    if (groups.empty() || groups.back().kind != kind || groups.back().n != n || groups.back().logv != logv)
+      groups.push_back(Group{kind, n, logv, 1, k, k, 0, 0, 0});
     Group& gr = groups.back();
     gr.k1 = k + 1;
     gr.RM = std::max(gr.RM, (int)rs[k]->in->rank);
@@ -962,7 +1003,7 @@ qst_status run_table(qst_handle* h, std::vector<const RunSpec*> rs, size_t* need
     const RunSpec& r = *rs[k];
     const qst_instance& in = *r.in;
     qst::OcInst& a = tab[k];
-    const bool oc = table_kind(r) == TK_OC;
+    const bool oc = table_kind(h, r) == TK_OC;
     a.atoms = in.atoms;
     a.alpha = in.weights;
     a.pc = reinterpret_cast<const uint64_t*>(ws + off_pc[k]);
@@ -1019,12 +1060,43 @@ qst_status run_table(qst_handle* h, std::vector<const RunSpec*> rs, size_t* need
   return QST_OK;
 }
 
+// Signature of a multi-instance call (FNV-1a over every instance's n, R, B and path, in order):
+// the key of its routing policy.
+uint64_t call_signature(const std::vector<RunSpec>& specs) {
+  uint64_t x = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    x ^= v;
+    x *= 1099511628211ull;
+  };
+  for (const RunSpec& r : specs) {
+    mix((uint64_t)r.in->n_qubits);
+    mix((uint64_t)r.in->rank);
+    mix((uint64_t)r.in->n_settings);
+    mix((uint64_t)resolve(r.path));
+  }
+  return x;
+}
+
+qst_status run_call_inner(qst_handle* h, const std::vector<RunSpec>& specs, size_t* need);
+
 qst_status run_call(qst_handle* h, const std::vector<RunSpec>& specs, size_t* need = nullptr) {
+  // the routing policy kept for this call's shapes (several instances) applies while it runs
+  const std::pair<int, int> saved = h->cur_policy;
+  if (specs.size() > 1 && !h->policies.empty()) {
+    auto it = h->policies.find(call_signature(specs));
+    if (it != h->policies.end()) h->cur_policy = it->second;
+  }
+  const qst_status st = run_call_inner(h, specs, need);
+  h->cur_policy = saved;
+  return st;
+}
+
+qst_status run_call_inner(qst_handle* h, const std::vector<RunSpec>& specs, size_t* need) {
   std::map<int, std::vector<const RunSpec*>> groups;
   std::vector<const RunSpec*> single;
   std::vector<const RunSpec*> onchip;
   for (const RunSpec& r : specs)
-    if (table_kind(r) != TK_NONE) onchip.push_back(&r);
+    if (table_kind(h, r) != TK_NONE) onchip.push_back(&r);
   if (!onchip.empty() && h->static_ws) {
     // without allocation the table path's buffers must fit the static scratch, else the staged path runs
     size_t oc_need = 0;
@@ -1249,8 +1321,10 @@ qst_status qst_create(int device, void* hip_stream, qst_handle** out) {
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   {
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-      h->num_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+      if (prop.multiProcessorCount > 0) h->num_cu = prop.multiProcessorCount;
+      h->arch = prop.gcnArchName;
+    }
   }
   if (hipMalloc(&h->dflag, sizeof(int)) != hipSuccess || hipHostMalloc(&h->hflag, sizeof(int)) != hipSuccess ||
       hipEventCreateWithFlags(&h->flag_ev, hipEventDisableTiming) != hipSuccess) {
@@ -1305,112 +1379,260 @@ static qst_status device_gate(qst_handle* h) {
   return QST_OK;
 }
 
+// ---------------------------------------------------------------- autotuning
+// Candidates are timed as whole backward calls (CE loss, weight and atom gradients) on the
+// handle's stream: one warm-up, then the median of three event-timed runs.  Their outputs go to
+// the end of the workspace, which is grown once to hold the largest candidate.
+static std::mutex g_tune_mu;
+static std::map<std::pair<std::string, std::tuple<int, int, int, int>>, qst_choice> g_choice_cache;
+static std::map<std::pair<std::string, uint64_t>, std::pair<int, int>> g_policy_cache;
+
+struct Timer {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  Timer() {
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+  }
+  ~Timer() {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  }
+};
+
+// Median time (ms) of the call, or a negative value when it fails (the candidate is then skipped).
+static double time_call(qst_handle* h, const std::vector<RunSpec>& specs, Timer& tm) {
+  if (run_call(h, specs) != QST_OK) return -1.0;
+  std::vector<float> ts;
+  for (int rep = 0; rep < 3; ++rep) {
+    hipEventRecord(tm.e0, h->stream);
+    if (run_call(h, specs) != QST_OK) return -1.0;
+    hipEventRecord(tm.e1, h->stream);
+    if (hipEventSynchronize(tm.e1) != hipSuccess) return -1.0;
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, tm.e0, tm.e1);
+    ts.push_back(ms);
+  }
+  std::sort(ts.begin(), ts.end());
+  return ts[1];
+}
+
+// Backward specs over `ins` with their outputs in the workspace after `base` (grown as needed).
+static qst_status tune_specs(qst_handle* h, const std::vector<qst_instance>& ins, qst_path path, size_t base,
+                             std::vector<RunSpec>& specs) {
+  size_t out = 0;
+  for (const qst_instance& in : ins)
+    out += al256((size_t)in.rank * ((size_t)1 << in.n_qubits) * 2 * elem_of(path)) + al256((size_t)in.rank * 8 + 8);
+  qst_status st = ensure_ws(h, base + out);
+  if (st != QST_OK) return st;
+  unsigned char* o = reinterpret_cast<unsigned char*>(h->ws) + base;
+  specs.assign(ins.size(), RunSpec{});
+  for (size_t k = 0; k < ins.size(); ++k) {
+    RunSpec& r = specs[k];
+    r.in = &ins[k];
+    r.path = path;
+    r.loss_kind = ins[k].freqs ? QST_LOSS_CE : QST_LOSS_NONE;
+    r.eps = 1e-8;
+    r.adjoint = true;
+    r.atom_grad = o;
+    o += al256((size_t)ins[k].rank * ((size_t)1 << ins[k].n_qubits) * 2 * elem_of(path));
+    r.weight_grad = reinterpret_cast<double*>(o);
+    r.loss = r.weight_grad + ins[k].rank;
+    o += al256((size_t)ins[k].rank * 8 + 8);
+  }
+  return QST_OK;
+}
+
+// One instance: its kernels (staged / atoms looped / fused slices), batch size and tile bits,
+// timed on a slice of at most 256 of its settings.
+static qst_status tune_shape(qst_handle* h, const qst_instance& in0, qst_path path) {
+  const auto key = shape_key(in0.n_qubits, in0.rank, in0.n_settings, path);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_choice_cache.find(std::make_pair(h->arch, key));
+    if (it != g_choice_cache.end()) {
+      h->choices[key] = it->second;
+      return QST_OK;
+    }
+  }
+  if (!in0.freqs) return QST_OK;  // the timing runs the CE backward
+  std::vector<qst_instance> ins(1, in0);
+  ins[0].n_settings = std::min(in0.n_settings, 256);
+  ins[0].settings_per_batch = 0;
+  const int n = in0.n_qubits, R = in0.rank;
+  Geometry g;
+  const bool staged_ok = make_geometry(h, n, R, in0.n_settings, path, g) == QST_OK;
+  h->last_error.clear();
+  // candidate list: (kind, S, t_fwd, t_adj, logv)
+  std::vector<qst_choice> cands;
+  auto cand = [&](int kind, int S, int tf, int ta, int lv) {
+    qst_choice c{};
+    c.kind = kind;
+    c.settings_per_batch = S;
+    c.tile_bits_fwd = tf;
+    c.tile_bits_adj = ta;
+    c.values_per_thread_log2 = lv;
+    cands.push_back(c);
+  };
+  cand(-1, 0, 0, 0, 0);  // the default
+  RunSpec probe{};
+  probe.in = &ins[0];
+  probe.path = path;
+  probe.atom_grad = h->ws;  // alignment probe only (the workspace base is 256-byte aligned)
+  if (staged_ok) cand(0, 0, 0, 0, 0);
+  if (oc_eligible(probe)) {
+    cand(1, 0, 0, 0, 5);
+    if (n == 13 || n == 14) cand(1, 0, 0, 0, 4);
+  }
+  if (((long long)R << n) <= 16384 && dev_table_eligible(probe)) cand(2, 0, 0, 0, 0);
+  if (staged_ok && g.n_hi > 0) {
+    const size_t per = (size_t)R * ((size_t)1 << n) * 2 * elem_of(path);
+    for (int S : {16, 32, 64, 128})
+      if (S <= ins[0].n_settings && (size_t)S * per <= (8ull << 30)) cand(0, S, 0, 0, 0);
+    for (int t : {13, 12})
+      if (t < 14 && g.n_hi <= (t == 13 ? 3 : 2) && t - g.n_hi <= g.n_lo) {
+        cand(0, 0, t, 0, 0);
+        cand(0, 0, 0, t, 0);
+      }
+  }
+  // workspace: the largest candidate, then the outputs
+  size_t need = 0;
+  std::vector<RunSpec> specs;
+  qst_status st = tune_specs(h, ins, path, 0, specs);
+  if (st != QST_OK) return st;
+  for (const qst_choice& c : cands) {
+    h->choices[key] = c;
+    size_t nd = 0;
+    if (run_call(h, specs, &nd) == QST_OK) need = std::max(need, nd);
+  }
+  h->last_error.clear();
+  st = tune_specs(h, ins, path, al256(need), specs);
+  if (st != QST_OK) return st;
+  Timer tm;
+  double best = -1.0, dflt = -1.0;
+  qst_choice chosen{};
+  chosen.kind = -1;
+  for (const qst_choice& c : cands) {
+    h->choices[key] = c;
+    const double ms = time_call(h, specs, tm);
+    h->last_error.clear();
+    if (ms < 0) continue;
+    if (c.kind == -1) dflt = ms;
+    if (best < 0 || ms < best) {
+      best = ms;
+      chosen = c;
+    }
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return set_err(h, QST_ERR_DEVICE, "autotune synchronise failed");
+  chosen.tuned = 1;
+  chosen.best_ms = best;
+  chosen.default_ms = dflt;
+  h->choices[key] = chosen;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_choice_cache[std::make_pair(h->arch, key)] = chosen;
+  return QST_OK;
+}
+
+// Several instances: the routing of the whole call (atoms looped for every eligible instance or
+// only where the atoms do not fit one work-group; fused slices on or off), timed on the call.
+static qst_status tune_policy(qst_handle* h, const qst_instance* inst, int n_inst, qst_path path) {
+  std::vector<qst_instance> ins(inst, inst + n_inst);
+  for (const qst_instance& in : ins)
+    if (!in.freqs) return QST_OK;
+  std::vector<RunSpec> specs;
+  qst_status st = tune_specs(h, ins, path, 0, specs);
+  if (st != QST_OK) return st;
+  const uint64_t sig = call_signature(specs);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_policy_cache.find(std::make_pair(h->arch, sig));
+    if (it != g_policy_cache.end()) {
+      h->policies[sig] = it->second;
+      return QST_OK;
+    }
+  }
+  const std::pair<int, int> pols[] = {{-1, -1}, {1, -1}, {-1, 0}, {1, 0}};
+  size_t need = 0;
+  for (const auto& p : pols) {
+    h->policies[sig] = p;
+    size_t nd = 0;
+    if (run_call(h, specs, &nd) == QST_OK) need = std::max(need, nd);
+  }
+  h->last_error.clear();
+  st = tune_specs(h, ins, path, al256(need), specs);
+  if (st != QST_OK) return st;
+  Timer tm;
+  double best = -1.0;
+  std::pair<int, int> chosen{-1, -1};
+  for (const auto& p : pols) {
+    h->policies[sig] = p;
+    const double ms = time_call(h, specs, tm);
+    h->last_error.clear();
+    if (ms >= 0 && (best < 0 || ms < best)) {
+      best = ms;
+      chosen = p;
+    }
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return set_err(h, QST_ERR_DEVICE, "autotune synchronise failed");
+  h->policies[sig] = chosen;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_policy_cache[std::make_pair(h->arch, sig)] = chosen;
+  return QST_OK;
+}
+
 qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_path path, int autotune) {
   qst_status st = common_checks(h, inst, n_inst, path);
   if (st != QST_OK) return st;
   path = resolve(path);
-  size_t need = 0;
   for (int i = 0; i < n_inst; ++i) {
     st = validate_instance(h, inst[i], path, false);
     if (st != QST_OK) return st;
     Geometry g;
     st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, path, g);
     if (st != QST_OK) return st;
-    mark(g, inst[i]);
-    int S = default_S(g);
-    if (h->device < 0) continue;
-    if (autotune && !pass_path(path) && g.n_hi > 0) {
-      // Time the fused pass on a slice of the settings for each candidate batch size
-      // (the same slice for every candidate, so the times compare directly).
-      const int cands[] = {8, 16, 32, 64, 128};
-      const int B_try = std::min(g.B, 256);
-      qst_instance sub = inst[i];
-      sub.n_settings = B_try;
-      void* grad = nullptr;
-      if (hipMalloc(&grad, (size_t)g.R * g.D * 2 * g.elem) != hipSuccess)
-        return set_err(h, QST_ERR_OOM, "autotune scratch");
-      double* wg = nullptr;
-      if (hipMalloc(&wg, (size_t)g.R * 8 + 8) != hipSuccess) {
-        hipFree(grad);
-        return set_err(h, QST_ERR_OOM, "autotune scratch");
-      }
-      {
-        // One arena for the largest candidate, so the search does not leave outgrown ones behind.
-        size_t most = 0;
-        for (int cS : cands) {
-          if (cS > B_try || (size_t)cS * g.R * g.D * 2 * g.elem > (16ull << 30)) break;
-          Geometry gc = g;
-          set_grid(h, gc, cS);
-          most = std::max(most, layout_ws(gc, cS, path, false).total);
-        }
-        st = ensure_ws(h, most);
-        if (st != QST_OK) {
-          hipFree(grad);
-          hipFree(wg);
-          return st;
-        }
-      }
-      float best = 1e30f;
-      int best_S = S;
-      hipEvent_t e0, e1;
-      hipEventCreate(&e0);
-      hipEventCreate(&e1);
-      for (int cS : cands) {
-        if (cS > B_try) break;
-        if ((size_t)cS * g.R * g.D * 2 * g.elem > (16ull << 30)) break;  // X and W hold S settings each
-        RunSpec rs{};
-        rs.in = &sub;
-        rs.path = path;
-        rs.loss_kind = inst[i].freqs ? QST_LOSS_CE : QST_LOSS_NONE;
-        rs.eps = 1e-8;
-        rs.atom_grad = grad;
-        rs.weight_grad = wg;
-        rs.loss = wg + g.R;
-        rs.adjoint = true;
-        rs.S_override = cS;
-        std::vector<float> times;
-        for (int rep = 0; rep < 3; ++rep) {
-          hipEventRecord(e0, h->stream);
-          st = run_instance(h, rs);
-          hipEventRecord(e1, h->stream);
-          if (st != QST_OK) break;
-          hipEventSynchronize(e1);
-          float ms = 0;
-          hipEventElapsedTime(&ms, e0, e1);
-          times.push_back(ms);
-        }
-        if (st != QST_OK) break;
-        std::sort(times.begin(), times.end());
-        if (times[1] < best) {
-          best = times[1];
-          best_S = cS;
-        }
-      }
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
-      hipFree(grad);
-      hipFree(wg);
-      if (st != QST_OK) return st;
-      S = best_S;
-      h->tuned_S[std::make_tuple(g.n, g.R, g.B, (int)path)] = S;
-    }
-    set_grid(h, g, std::min(S, g.B));
-    need = std::max(need, layout_ws(g, std::min(S, g.B), path, false).total);
   }
   st = device_gate(h);
   if (st != QST_OK) return st;
-  {
-    // the same call with these instances: batches of small ones need their own layout
-    std::vector<RunSpec> specs(n_inst);
-    for (int i = 0; i < n_inst; ++i) {
-      specs[i].in = &inst[i];
-      specs[i].path = path;
-      specs[i].adjoint = true;
-    }
-    st = run_call(h, specs, &need);
+  if (autotune && !pass_path(path)) {
+    if (capturing(h->stream)) return set_err(h, QST_ERR_CAPTURE, "autotune outside stream capture");
+    st = n_inst == 1 ? tune_shape(h, inst[0], path) : tune_policy(h, inst, n_inst, path);
     if (st != QST_OK) return st;
   }
+  // the same call with these instances, as the compute calls will run it
+  size_t need = 0;
+  std::vector<RunSpec> specs(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    specs[i].in = &inst[i];
+    specs[i].path = path;
+    specs[i].adjoint = true;
+  }
+  st = run_call(h, specs, &need);
+  if (st != QST_OK) return st;
   return ensure_ws(h, need);
+}
+
+qst_status qst_plan_choice(qst_handle* h, const qst_instance* inst, qst_path path, int set, qst_choice* choice) {
+  qst_status st = common_checks(h, inst, 1, path);
+  if (st != QST_OK) return st;
+  if (!choice) return set_err(h, QST_ERR_INVALID_ARG, "null choice");
+  path = resolve(path);
+  st = validate_instance(h, *inst, path, false);
+  if (st != QST_OK) return st;
+  const auto key = shape_key(inst->n_qubits, inst->rank, inst->n_settings, path);
+  if (set) {
+    if (choice->kind < -1 || choice->kind > 2 || choice->settings_per_batch < 0 || choice->tile_bits_fwd < 0 ||
+        choice->tile_bits_adj < 0 || choice->values_per_thread_log2 < 0)
+      return set_err(h, QST_ERR_INVALID_ARG, "choice fields out of range");
+    h->choices[key] = *choice;
+    return QST_OK;
+  }
+  auto it = h->choices.find(key);
+  if (it != h->choices.end()) {
+    *choice = it->second;
+  } else {
+    *choice = qst_choice{};
+    choice->kind = -1;
+  }
+  return QST_OK;
 }
 
 qst_status qst_forward(qst_handle* h, const qst_instance* inst, int n_inst, void* const* probs, double* loss,
