@@ -405,6 +405,15 @@ __device__ __forceinline__ int nonz_count(uint64_t pc, int n) {
   return n - __popcll(zbits);
 }
 
+// A setting's code word through the constant address space: with a uniform index the load is a
+// scalar load, counted apart from the vector loads in flight (waiting for it then does not wait
+// for a prefetch issued before it).
+__device__ __forceinline__ uint64_t load_code(const uint64_t* pc, int b) {
+  using cu64ptr = const __attribute__((address_space(4))) uint64_t*;
+  const int bu = __builtin_amdgcn_readfirstlane(b);
+  return ((cu64ptr)(pc))[bu];
+}
+
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));

@@ -49,9 +49,6 @@ __device__ __forceinline__ int oc_find(int k0, int k1, int i, F first) {
 }
 
 __device__ __forceinline__ float4 ld_f4(const float* p) { return *reinterpret_cast<const float4*>(p); }
-__device__ __forceinline__ void st_f4(float* p, float a, float b, float c, float d) {
-  *reinterpret_cast<float4*>(p) = make_float4(a, b, c, d);
-}
 
 }  // namespace
 
@@ -98,7 +95,7 @@ __global__ __launch_bounds__((oc_threads<NB, LOGV>())) void k_oc_fwd(const OcIns
       const int s = sb + vec;
       const bool valid = s < s_end;
       const int b = valid ? s : s_beg;  // a spare vector repeats a setting and writes nothing
-      const uint64_t pc = uniform_u64(a.pc[b]);
+      const uint64_t pc = load_code(a.pc, b);
       const uint32_t ym = ymask_of(pc, NB);
       const float s2 = (float)ldexp(1.0, -nonz_count(pc, NB));
       float acc[V];
@@ -117,22 +114,35 @@ __global__ __launch_bounds__((oc_threads<NB, LOGV>())) void k_oc_fwd(const OcIns
 #pragma unroll
         for (int i = 0; i < V; ++i) acc[i] = fma(al, fma(x[i], x[i], y[i] * y[i]), acc[i]);
       }
-      // Outcomes u0 .. u0 + 31 of this thread (final layout lo = 0), four at a time.
-      const long long row = (long long)b * D + ((long long)tau << LOGV);
+      // The atom sum goes through this vector's LDS plane so that consecutive lanes take
+      // consecutive outcomes u = tau + e 2^(n-LOGV): the data row and the outputs are then read
+      // and written in whole lines.  (The last rotation's transposes are done with the plane.)
+      {
+        float* prow = re + pad_base<LOGV, 0>(tau);
+#pragma unroll
+        for (int i = 0; i < V; ++i) prow[pad_off<0>(i)] = acc[i];
+      }
+      if constexpr (WL)
+        wave_sync();
+      else
+        __syncthreads();
+      const long long row = (long long)b * D;
       const bool gen = a.grad_p != nullptr;
+      const bool data = a.freqs != nullptr && !gen;
 #pragma unroll
-      for (int q = 0; q < V / 4; ++q) {
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f), w = v;
-        if (a.freqs != nullptr && !gen) v = ld_f4(a.freqs + row + 4 * q);
-        if (a.pbase != nullptr) w = ld_f4(a.pbase + row + 4 * q);
-        const float d[4] = {v.x, v.y, v.z, v.w};
-        const float pb[4] = {w.x, w.y, w.z, w.w};
-        float p[4], gs[4], gn[4];
+      for (int e0 = 0; e0 < V; e0 += 8) {
+        float d[8], pb[8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          float pv = acc[4 * q + e] * s2;
+        for (int e = 0; e < 8; ++e) {
+          const long long u = tau + (long long)(e0 + e) * TA;
+          d[e] = data ? a.freqs[row + u] : 0.0f;
+          pb[e] = a.pbase != nullptr ? a.pbase[row + u] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int u = tau + (e0 + e) * TA;
+          float pv = re[pad32(u)] * s2;
           if (a.pbase != nullptr) pv += pb[e];
-          p[e] = pv;
           float g = 0.0f;
           if (a.loss_kind == 0) {
             if (d[e] > 0.0f) {
@@ -147,15 +157,17 @@ __global__ __launch_bounds__((oc_threads<NB, LOGV>())) void k_oc_fwd(const OcIns
             if (valid) loss_acc += (double)(0.5f * rr * rr);
             g = rr * inv_b;
           }
-          gs[e] = g * s2;
-          gn[e] = -g;
-        }
-        if (valid) {
-          if (a.probs != nullptr) st_f4(a.probs + row + 4 * q, p[0], p[1], p[2], p[3]);
-          if (a.G != nullptr) st_f4(a.G + row + 4 * q, gs[0], gs[1], gs[2], gs[3]);
-          if (a.gneg != nullptr) st_f4(a.gneg + row + 4 * q, gn[0], gn[1], gn[2], gn[3]);
+          if (valid) {
+            if (a.probs != nullptr) a.probs[row + u] = pv;
+            if (a.G != nullptr) a.G[row + u] = g * s2;
+            if (a.gneg != nullptr) a.gneg[row + u] = -g;
+          }
         }
       }
+      if constexpr (WL)
+        wave_sync();  // the plane's reads precede the next rotation's writes
+      else
+        __syncthreads();
     }
     // Loss partial of this item to slot j; weight-gradient rows of the slots pass A does not
     // write (j >= nA) are zeroed here, so every slot is defined.
@@ -206,8 +218,22 @@ __global__ __launch_bounds__((oc_threads<NB, LOGV>()), (LOGV == 5 ? 2 : 4)) void
     const int k = oc_find(k0, k1, item, [&](int kk) { return tab[kk].itemA0; });
     const OcInst& a = tab[k];
     const int j = item - a.itemA0;
-    const int slice = j / a.ntile;
-    const int tile = j - slice * a.ntile;
+    // Items map to (slice, atom tile) so that the tiles of one slice share j mod 8: work-groups
+    // are dispatched to the eight XCDs in turn, so those tiles run on one XCD, close in time, and
+    // the slice's rows of 2^-k dL/dp come from that XCD's L2 after the first tile's read.
+    int slice, tile;
+    {
+      const int full = (a.nA / 8) * 8;  // slices in whole groups of eight
+      if (j < full * a.ntile) {
+        const int grp = j / (8 * a.ntile), rem = j - grp * 8 * a.ntile;
+        slice = grp * 8 + (rem & 7);
+        tile = rem >> 3;
+      } else {
+        const int jj = j - full * a.ntile;
+        slice = full + jj / a.ntile;
+        tile = jj - (slice - full) * a.ntile;
+      }
+    }
     const int R = a.R;
     const int r = tile * VPW + vec;
     const bool active = r < R;
@@ -226,7 +252,7 @@ __global__ __launch_bounds__((oc_threads<NB, LOGV>()), (LOGV == 5 ? 2 : 4)) void
     const bool gen = a.grad_p != nullptr;
     const float* gsrc = gen ? a.grad_p : a.G;
     for (int b = s_beg; b < s_end; ++b) {
-      const uint64_t pc = uniform_u64(a.pc[b]);
+      const uint64_t pc = load_code(a.pc, b);
       const uint32_t ym = ymask_of(pc, NB);
       const float s2 = (float)ldexp(1.0, -nonz_count(pc, NB));
       float x[V], y[V];
@@ -349,7 +375,7 @@ __global__ __launch_bounds__(512) void k_fs(const OcInst* __restrict__ tab, int 
     for (int i = 0; i < V; ++i) ax[i] = ay[i] = 0.0f;
     double loss_acc = 0.0, h_acc = 0.0;
     for (int b = s_beg; b < s_end; ++b) {
-      const uint64_t pc = uniform_u64(a.pc[b]);
+      const uint64_t pc = load_code(a.pc, b);
       const uint32_t ym = ymask_of(pc, NB);
       const float s2 = (float)ldexp(1.0, -nonz_count(pc, NB));
       const long long row = (long long)b * D;

@@ -217,6 +217,7 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
   auto voff = [&](const LoArgs& a, uint32_t cb) { return (uint32_t)(((long long)atom * a.D + pos0) * cb); };
 
   double loss_acc = 0.0, h_acc = 0.0;
+  T al_cur = T(0);         // this thread's atom weight in the current instance
   int cur = -1;            // instance whose partials are being accumulated
   uint32_t touched = 0u;   // instances this work-group wrote partials for
 
@@ -289,6 +290,9 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
     if (k != cur) {
       if (cur >= 0) flush(cur);
       cur = k;
+      // loaded when the instance changes, not per chunk: a vector load here would have to
+      // wait for the next chunk's prefetch, which is issued before it
+      al_cur = atom < m.a[k].R ? (T)m.a[k].alpha[atom] : T(0);
     }
     const LoArgs& a = m.a[k];
     const int cl = c - m.begin[k];
@@ -296,9 +300,8 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
     const int h = cl & ((1 << a.n_hi) - 1);
     const int b = a.b0 + s;
     const long long D = a.D;
-    const bool active = atom < a.R;
-    const T al = active ? (T)a.alpha[atom] : T(0);
-    const uint64_t pc = uniform_u64(a.pc[b]);
+    const T al = al_cur;
+    const uint64_t pc = load_code(a.pc, b);
     const T s2 = GEN ? T(1) : (T)ldexp(1.0, -nonz_count(pc, a.n));
     const cfptr um = GEN ? to_const(a.um + (size_t)b * a.n * 8) : nullptr;
     const double Bd = (double)a.B;
@@ -388,7 +391,19 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
     // prefetched with the chunk; the rest (and the base values) are loaded in groups of
     // NG whose loads are all in flight before the first of them is used.
     constexpr int NG = 4;
-    for (int j0 = 0; tid + j0 * nthr < U; j0 += NG) {
+    // Dense data without base probabilities: the first NPF outcomes take their data from the
+    // chunk's prefetch, so nothing here waits for memory (a wait on a load issued after the
+    // next chunk's prefetch would wait for that prefetch too).
+    int j_first = 0;
+    if (!sparse && pbp == nullptr) {
+#pragma unroll
+      for (int jj = 0; jj < NPF; ++jj) {
+        const int u = tid + jj * nthr;
+        if (u < U) outcome(u, row_data ? fv[jj] : T(0), T(0));
+      }
+      j_first = NPF;
+    }
+    for (int j0 = j_first; tid + j0 * nthr < U; j0 += NG) {
       T dg[NG], bg[NG];
 #pragma unroll
       for (int jj = 0; jj < NG; ++jj) {
@@ -399,7 +414,7 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
           if (sparse) {
             dg[jj] = gb[pad32(u)];
           } else if (row_data) {
-            if (jj < NPF && j0 == 0)
+            if (jj < NPF && j0 == 0)  // only when the prefetched outcomes were not taken above
               dg[jj] = fv[jj < NPF ? jj : 0];
             else
               dg[jj] = gp ? gp[row + u] : (T)a.freqs[row + u];
@@ -579,7 +594,7 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
       if (s_lo < s_hi) ecur = lane_e(s_lo);
     }
     for (int s = s_lo; s < s_hi; ++s) {
-      const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
+      const uint64_t pc = load_code(a.pc, a.b0 + s);
       T x[V], y[V];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
@@ -638,7 +653,7 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         }
         apply_gphase<true, LOGV>(x, y, cbase | tf, a.n, offf, PhaseLanes{e});
       } else {
-        const uint64_t pc = uniform_u64(a.pc[a.b0 + s]);
+        const uint64_t pc = load_code(a.pc, a.b0 + s);
         const uint32_t ym = ymask_of(pc, a.n);
         xform_xz<LOGV, M0>(x, y, layout_codes<LOGV>(pc, LO0, LO0, TB, C, n_lo));
         if constexpr (TWO) {
@@ -662,21 +677,24 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         body(s + 1, qx, qy, qe);
       }
     }
-    // one split: accumulate into the gradient; several: this split's sum to its slice
+    // one split: accumulate into the gradient; several: this split's sum to its slice.  The
+    // gradient tile's loads are all issued before the first is used (the condition is uniform,
+    // so it is tested once rather than around every load).
     const bool whole = a.nsplit == 1;
     C2* out = whole ? reinterpret_cast<C2*>(a.dst) : reinterpret_cast<C2*>(a.part) + (long long)sp * a.R * D;
     const rsrc_t rg = make_rsrc(out + origin, vbytes);
+    if (whole && !a.first) {
+      T gx[V], gy[V];
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-      const uint32_t so = offf(i) * CB;
-      if (whole && !a.first) {
-        T gx, gy;
-        bload2(gx, gy, rg, vof, so);
-        ax[i] += gx;
-        ay[i] += gy;
+      for (int i = 0; i < V; ++i) bload2(gx[i], gy[i], rg, vof, offf(i) * CB);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        ax[i] += gx[i];
+        ay[i] += gy[i];
       }
-      bstore2(ax[i], ay[i], rg, vof, so);
     }
+#pragma unroll
+    for (int i = 0; i < V; ++i) bstore2(ax[i], ay[i], rg, vof, offf(i) * CB);
   }
 }
 
