@@ -92,7 +92,9 @@ typedef enum {
   QST_PATH_TILE_F16 = 4,      /* one HBM pass per 4-qubit group: 16x16 complex Kronecker
                                  tiles on the matrix cores, FP16 operands (scaled per
                                  16x16 block), FP32 accumulation; complex64 atoms        */
-  QST_PATH_TILE_BF16 = 5,     /* the same with BF16 operands (high and low parts)         */
+  QST_PATH_TILE_BF16 = 5,     /* the same with BF16 operands (high and low parts); tiles
+                                 with FP32 operands are not offered: at the FP32 matrix
+                                 rate they cost more than the FP32 butterflies           */
   QST_PATH_BUTTERFLY_BF16 = 6 /* staged butterflies in FP32 with the setting-batch
                                  intermediates stored in BF16: half their HBM traffic;
                                  complex64 atoms, error about 1e-3 (tolerance 1e-2)      */
@@ -100,8 +102,12 @@ typedef enum {
 
 /* One independent tomography instance (the arguments of the paper's problem
  * statement: atoms, weights, descriptor-level settings, observed frequencies).
- *   n_qubits  N, 1..20 (D = 2^N)
- *   rank      R, 1..16 (the atom count R_t)
+ *   n_qubits  N, 1..20 (D = 2^N).  The staged kernels split the index bits into one
+ *             low and one high pass of at most 2^14 amplitudes per tile and 2^10 rows,
+ *             which covers N <= 20 at every rank; larger N would need a third pass over
+ *             the high bits, not built, so larger N returns QST_ERR_SHAPE.
+ *   rank      R, 1..16 (the atom count R_t; the low pass holds all R atoms of a chunk,
+ *             R 2^(low bits) <= 2^14, so R <= 16 keeps at least ten low bits)
  *   n_settings B >= 1
  *   atoms     [R][D] complex64 (complex128 for QST_PATH_BUTTERFLY_F64), 8-byte
  *             (16-byte) aligned
