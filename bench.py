@@ -157,6 +157,81 @@ def read_traffic(kernel_kind: str, workload: str):
     return float(d["bytes_per_launch"])
 
 
+def step_inputs(seed: int, n: int, R: int, B: int, R_true: int):
+    """Host inputs of the timed step: model atoms and weights, settings, truth weights."""
+    rng = synth.make_rng(seed)
+    atoms = synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64)
+    w = synth.dirichlet_weights(rng, R)
+    s = synth.random_settings(rng, B, n)
+    w_true = synth.dirichlet_weights(rng, R_true)
+    return atoms, w, s, w_true
+
+
+def step_instance(api, dev, seed: int, n: int, R: int, B: int, shots: int, R_true: int, host=None):
+    """The timed step's instance on the device (frequencies drawn on the device)."""
+    import torch
+
+    atoms, w, s, w_true = host if host is not None else step_inputs(seed, n, R, B, R_true)
+    freqs = synth.porter_thomas_freqs_torch(seed + 3, B, 1 << n, w_true, shots, dev)
+    return api.Instance(torch.from_numpy(atoms).to(dev), torch.from_numpy(w).to(dev), torch.from_numpy(s).to(dev),
+                        freqs)
+
+
+def refactor_extra(api, h, inst, seed: int) -> dict:
+    """The spectral refactor (Lanczos k = 30, L = 8) on the step's instance, with its G v
+    products grouped by the settings' high-bit codes (the default) and through the staged
+    path (QST_GV_GROUPED=0): wall time of one call after a warm-up call, the mean G v product
+    from the library's event brackets, and the agreement of the two runs' Ritz values."""
+    import torch
+
+    n = int(inst.settings.shape[1])
+    D = 1 << n
+    B = int(inst.settings.shape[0])
+    v0 = torch.from_numpy(synth.haar_atoms(synth.make_rng(seed), 1, D)[0]).to(inst.atoms.device)
+    runs = {}
+    old = os.environ.get("QST_GV_GROUPED")
+    try:
+        for name, flag in (("grouped", "1"), ("staged", "0")):
+            os.environ["QST_GV_GROUPED"] = flag
+            api.qst_refactor(h, inst, api.LOSS_CE, 1e-8, 0.5, 1e-3, 1e-3, 8, 30, v0)
+            torch.cuda.synchronize()
+            h.profile(True)
+            h.profile_read(reset=True)
+            t0 = time.perf_counter()
+            res = api.qst_refactor(h, inst, api.LOSS_CE, 1e-8, 0.5, 1e-3, 1e-3, 8, 30, v0)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3
+            prof = h.profile_read(reset=True)
+            h.profile(False)
+            runs[name] = (wall, prof["gv"], res["ritz_vals"].cpu().numpy(), int(res["R"][0]))
+    finally:
+        if old is None:
+            os.environ.pop("QST_GV_GROUPED", None)
+        else:
+            os.environ["QST_GV_GROUPED"] = old
+    n_hi = max(0, n - 14)
+    groups = len({bytes(r) for r in inst.settings[:, :n_hi].cpu().numpy()}) if n_hi > 0 else B
+    wall, (cnt, tot), rv, rout = runs["grouped"]
+    wall_s, (cnt_s, tot_s), rv_s, _ = runs["staged"]
+    gv_ms = tot / max(cnt, 1)
+    # grouped G v bytes: X and W of each group written and read once (stage A, low stage,
+    # stage C), the sensitivities of every setting read once, v read and G v written
+    gv_bytes = 4.0 * groups * D * 8 + B * D * 4 + 2.0 * D * 8
+    lead = np.abs(rv[:2] - rv_s[:2]) / np.abs(rv_s[:2])
+    return {
+        "refactor_ms": round(wall, 1),
+        "refactor_R_out": rout,
+        "gv_products": cnt,
+        "gv_ms": round(gv_ms, 2),
+        "gv_groups": groups,
+        "gv_model_bytes": gv_bytes,
+        "gv_model_GBps": round(gv_bytes / (gv_ms * 1e-3) / 1e9, 1),
+        "refactor_ms_staged_gv": round(wall_s, 1),
+        "gv_ms_staged": round(tot_s / max(cnt_s, 1), 2),
+        "ritz_rel_diff_grouped_vs_staged": float(lead.max()),
+    }
+
+
 def solve_extra(api, h, dev, seed: int, slots: int = 100):
     """The rank-adaptive iteration (Algorithm 1) on the n=14, R_max=8, B=1000 workload: truth of
     rank 4, frequencies Poisson(1e5 p)/1e5 from the library's own forward of the truth, start
@@ -345,7 +420,7 @@ def main():
                          "BF16 intermediates (1e-2 variant)")
     ap.add_argument("--batch", type=int, default=0, help="settings per batch (0: library default or --autotune)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only a 1 GiB device copy (counter scale)")
-    ap.add_argument("--only", choices=["uneven64", "solve", "onchip"], default=None,
+    ap.add_argument("--only", choices=["uneven64", "solve", "onchip", "refactor"], default=None,
                     help="run only one extra (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -367,6 +442,9 @@ def main():
             res = uneven_batch_extra(api, h, dev, seed + 21)
         elif args.only == "onchip":
             res = onchip_extra(api, h, dev, seed + 41)
+        elif args.only == "refactor":
+            inst = step_instance(api, dev, seed, n, R, B, shots, wl["R_true"])
+            res = refactor_extra(api, h, inst, seed + 11)
         else:
             res = solve_extra(api, h, dev, seed + 31)
         print(json.dumps({args.only: res}), flush=True)
@@ -384,11 +462,7 @@ def main():
         print(json.dumps({"copy_bytes": x.numel() * 4}))
         return
 
-    rng = synth.make_rng(seed)
-    atoms = synth.haar_atoms(rng, R, D, dtype=np.complex64)
-    w = synth.dirichlet_weights(rng, R)
-    s = synth.random_settings(rng, B, n)
-    w_true = synth.dirichlet_weights(rng, wl["R_true"])
+    atoms, w, s, w_true = step_inputs(seed, n, R, B, wl["R_true"])
 
     cpu = cpu_ref = None
     if not args.no_cpu_baseline:
@@ -405,9 +479,8 @@ def main():
     from paper_2607_19577_amd import api
 
     dev = torch.device("cuda:0")
-    freqs = synth.porter_thomas_freqs_torch(seed + 3, B, D, w_true, shots, dev)
-    inst = api.Instance(torch.from_numpy(atoms).to(dev), torch.from_numpy(w).to(dev), torch.from_numpy(s).to(dev),
-                        freqs)
+    inst = step_instance(api, dev, seed, n, R, B, shots, wl["R_true"], (atoms, w, s, w_true))
+    freqs = inst.freqs
     grad = torch.empty_like(inst.atoms)
     h = api.Handle(0)
     if args.autotune:
@@ -583,12 +656,7 @@ def main():
         extras["forward_probs_loss_ms"] = round(fwd_ms, 1)
         extras["atom_trial_ms"] = round(trial_ms, 1)
         extras["atom_trial_speedup_vs_forward"] = round(fwd_ms / trial_ms, 2)
-        v0 = torch.from_numpy(synth.haar_atoms(synth.make_rng(seed + 11), 1, D)[0]).to(dev)
-        t0 = time.perf_counter()
-        res = api.qst_refactor(h, inst, api.LOSS_CE, 1e-8, 0.5, 1e-3, 1e-3, 8, 30, v0)
-        torch.cuda.synchronize()
-        extras["refactor_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
-        extras["refactor_R_out"] = int(res["R"][0])
+        extras.update(refactor_extra(api, h, inst, seed + 11))
 
     if not args.no_extras:
         extras["n14_r8_b1000_onchip"] = onchip_extra(api, h, dev, seed + 41)

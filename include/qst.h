@@ -373,7 +373,8 @@ qst_status qst_state_error(qst_handle* h, int n_qubits, const void* atoms_a, con
  * of HIP events on its stream, grouped by stage kind:
  *   0 descriptor decode, 1 high-bit tile stage (forward), 2 fused low-bit stage,
  *   3 high-bit tile stage (adjoint, gradient accumulation), 4 reductions and
- *   epilogues, 5 other (reweight, refactor helpers, reference path).
+ *   epilogues, 5 other (reweight, refactor helpers, reference path), 6 one whole G v
+ *   product of qst_refactor (its stages are then not counted under 1..4).
  * qst_profile_read synchronises the stream and returns, for one kind, the number of
  * launches and their summed event-to-event milliseconds since the last reset
  * (reset != 0 clears every kind).  Enabling allocates events; launches made while

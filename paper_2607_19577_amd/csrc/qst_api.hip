@@ -57,6 +57,8 @@ struct qst_handle {
   };
   std::vector<Mark> marks;
   int open_kind = -1;
+  bool prof_outer = false;  // a whole G v product is bracketed: its stages are not
+  int gv_occupancy = 0;     // work-groups per CU of the grouped G v low stage
   hipEvent_t open_ev = nullptr;
   // no-allocation mode (qst_backward_static): ws points at the device's static scratch
   void* static_scratch = nullptr;  // this device's copy of `scratch` (from qst_create)
@@ -67,7 +69,8 @@ namespace {
 
 constexpr int G1 = 256;  // first-level reduction width
 
-enum { PK_DECODE = 0, PK_HI_FWD = 1, PK_LO = 2, PK_HI_ADJ = 3, PK_REDUCE = 4, PK_OTHER = 5 };
+enum { PK_DECODE = 0, PK_HI_FWD = 1, PK_LO = 2, PK_HI_ADJ = 3, PK_REDUCE = 4, PK_OTHER = 5, PK_GV = 6 };
+constexpr int kProfKinds = 7;
 
 hipEvent_t prof_event(qst_handle* h) {
   if (h->ev_next == h->ev_pool.size()) {
@@ -86,7 +89,7 @@ bool capturing(hipStream_t st) {
 
 // Bracket the next launch(es) of one stage kind.
 void prof_begin(qst_handle* h, int kind) {
-  if (!h->prof || h->static_ws || capturing(h->stream)) return;
+  if (!h->prof || h->static_ws || h->prof_outer || capturing(h->stream)) return;
   hipEvent_t e = prof_event(h);
   if (!e) return;
   hipEventRecord(e, h->stream);
@@ -95,12 +98,23 @@ void prof_begin(qst_handle* h, int kind) {
 }
 
 void prof_end(qst_handle* h) {
-  if (!h->prof || h->static_ws || h->open_kind < 0 || capturing(h->stream)) return;
+  if (!h->prof || h->static_ws || h->prof_outer || h->open_kind < 0 || capturing(h->stream)) return;
   hipEvent_t e = prof_event(h);
   if (!e) return;
   hipEventRecord(e, h->stream);
   h->marks.push_back({h->open_kind, h->open_ev, e});
   h->open_kind = -1;
+}
+
+// Bracket one whole G v product of the refactor (the stages inside it are not bracketed).
+void prof_outer_begin(qst_handle* h) {
+  h->prof_outer = false;
+  prof_begin(h, PK_GV);
+  h->prof_outer = true;
+}
+void prof_outer_end(qst_handle* h) {
+  h->prof_outer = false;
+  prof_end(h);
 }
 
 qst_status set_err(qst_handle* h, qst_status s, const std::string& msg) {
@@ -835,6 +849,18 @@ int table_kind(const qst_handle* h, const RunSpec& r) {
 // item when the instance runs alone, no slice below QST_OC_SLICE_MIN settings (default 16),
 // which bounds the slice partials written to HBM at 16 / S_min bytes per (setting, atom)
 // amplitude.
+// QST_GV_GROUPED=0 (read at every refactor call) sends the G v products through the staged
+// path instead of the grouped low stage.
+bool gv_grouped_on() {
+  const char* e = std::getenv("QST_GV_GROUPED");
+  return !(e && e[0] == '0');
+}
+
+int gv_occ(qst_handle* h) {
+  if (h->gv_occupancy <= 0) h->gv_occupancy = qst::gv_blocks_per_cu(5);
+  return h->gv_occupancy;
+}
+
 int env_oc_slice_min() {
   static const int v = [] {
     const int x = env_int("QST_OC_SLICE_MIN", 0);
@@ -1279,7 +1305,7 @@ qst_status qst_profile_enable(qst_handle* h, int enable) {
 
 qst_status qst_profile_read(qst_handle* h, int kind, int64_t* launches, double* total_ms, int reset) {
   if (!h || !launches || !total_ms) return QST_ERR_INVALID_ARG;
-  if (kind < 0 || kind > 5) return set_err(h, QST_ERR_INVALID_ARG, "kind must be in 0..5");
+  if (kind < 0 || kind >= kProfKinds) return set_err(h, QST_ERR_INVALID_ARG, "kind must be in 0..6");
   *launches = 0;
   *total_ms = 0.0;
   if (h->device < 0) return QST_OK;
@@ -1892,6 +1918,12 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
   o = al256(o + 64 * 1024);
   const size_t off_dpart = o;
   o = al256(o + (size_t)(k_max + R + 2) * G1 * 2 * 8);
+  // G v with the settings grouped by their high codes (one vector, FP32, Pauli settings,
+  // 14 low bits): pattern code words, member code words, member order, group starts and the
+  // patterns' settings rows.
+  const bool grouped = gv_grouped_on() && c64 && !inst->unitaries && g1.n_hi > 0 && g1.n_lo == qst::kGvLoBits;
+  const size_t off_grp = o;
+  if (grouped) o = al256(o + (size_t)B * 8 * 2 + (size_t)B * 4 * 2 + 4 + (size_t)B * n + 256);
   st = ensure_ws(h, o);
   if (st != QST_OK) return st;
   unsigned char* ws = reinterpret_cast<unsigned char*>(h->ws);
@@ -1905,6 +1937,7 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
   double* dpart = reinterpret_cast<double*>(ws + off_dpart);
   double* dots = misc + 16;
   double* coef = misc + 16 + 2 * 512;
+  h->prof_outer = false;
 
   // 1. -g of the current state (dL/dp), written by the forward pass.
   {
@@ -1919,6 +1952,122 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
     st = run_instance(h, rs, 0, nullptr);
     if (st != QST_OK) return st;
   }
+  // Grouping of the settings by their high codes (qubits 0 .. n_hi - 1, i.e. index bits
+  // n - 1 .. n_lo; codes above 2 read as Z, as the decode does).
+  int n_pat = 0;
+  uint64_t *pc_pat = nullptr, *pc_all = nullptr;
+  int *perm_d = nullptr, *goff_d = nullptr;
+  if (grouped) {
+    unsigned char* gb = ws + off_grp;
+    pc_pat = reinterpret_cast<uint64_t*>(gb);
+    pc_all = pc_pat + B;
+    perm_d = reinterpret_cast<int*>(pc_all + B);
+    goff_d = perm_d + B;
+    uint8_t* set_pat = reinterpret_cast<uint8_t*>(goff_d + B + 1);
+    std::vector<uint8_t> sh((size_t)B * n);
+    QST_HIP(hipMemcpyAsync(sh.data(), inst->settings, sh.size(), hipMemcpyDeviceToHost, s));
+    QST_HIP(hipStreamSynchronize(s));
+    const int nh = g1.n_hi;
+    std::vector<uint32_t> key(B);
+    for (int bb = 0; bb < B; ++bb) {
+      uint32_t kk = 0;
+      for (int j = 0; j < nh; ++j) kk = kk * 3u + std::min<uint32_t>(sh[(size_t)bb * n + j], 2u);
+      key[bb] = kk;
+    }
+    std::vector<int> perm(B), goff;
+    for (int bb = 0; bb < B; ++bb) perm[bb] = bb;
+    std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return key[x] < key[y]; });
+    std::vector<uint8_t> sp;
+    for (int i = 0; i < B; ++i) {
+      if (i > 0 && key[perm[i]] == key[perm[i - 1]]) continue;
+      goff.push_back(i);
+      for (int j = 0; j < n; ++j) sp.push_back(j < nh ? std::min<uint8_t>(sh[(size_t)perm[i] * n + j], 2) : 2);
+    }
+    n_pat = (int)goff.size();
+    goff.push_back(B);
+    QST_HIP(hipMemcpyAsync(perm_d, perm.data(), (size_t)B * 4, hipMemcpyHostToDevice, s));
+    QST_HIP(hipMemcpyAsync(goff_d, goff.data(), goff.size() * 4, hipMemcpyHostToDevice, s));
+    QST_HIP(hipMemcpyAsync(set_pat, sp.data(), sp.size(), hipMemcpyHostToDevice, s));
+    QST_HIP(qst::launch_decode(set_pat, n_pat, n, pc_pat, h->dflag, s));
+    QST_HIP(qst::launch_decode(inst->settings, B, n, pc_all, h->dflag, s));
+    QST_HIP(hipStreamSynchronize(s));  // the host vectors above go out of scope
+  }
+  // One G v product, gv = sum_b V_b^dagger diag(2^-k_b (-g_b)) V_b vin: grouped (stage A on
+  // the patterns, the grouped low stage, stage C on the patterns) or through the staged path.
+  auto gv_product = [&]() -> qst_status {
+    if (!grouped) {
+      qst_instance one_inst = *inst;
+      one_inst.rank = 1;
+      one_inst.atoms = vin;
+      one_inst.weights = misc;
+      RunSpec rs{};
+      rs.in = &one_inst;
+      rs.path = path;
+      rs.loss_kind = QST_LOSS_NONE;
+      rs.grad_p = gneg;
+      rs.atom_grad = gv;
+      rs.adjoint = true;
+      rs.S_override = S1;
+      return run_instance(h, rs, L1.pc, nullptr);
+    }
+    void* XP = ws + L1.X;
+    void* WP = ws + L1.W;
+    const int gv_grid_max = h->num_cu * gv_occ(h);
+    for (int p0 = 0; p0 < n_pat; p0 += S1) {
+      const int Sp = std::min(S1, n_pat - p0);
+      qst::HiArgs ha{};
+      ha.src = vin;
+      ha.dst = XP;
+      ha.pc = pc_pat;
+      ha.D = D;
+      ha.R = 1;
+      ha.n = n;
+      ha.n_lo = g1.n_lo;
+      ha.n_hi = g1.n_hi;
+      ha.t = g1.t;
+      ha.c = g1.c;
+      ha.b0 = p0;
+      ha.S = Sp;
+      ha.nsplit = split_of(h, g1, g1.c, Sp);
+      QST_HIP(qst::launch_stage_hi(g1, ha, false, s));
+      qst::GvArgs ga{};
+      ga.X = reinterpret_cast<const float2*>(XP);
+      ga.W = reinterpret_cast<float2*>(WP);
+      ga.pc = pc_all;
+      ga.perm = perm_d;
+      ga.goff = goff_d;
+      ga.g = reinterpret_cast<const float*>(gneg);
+      ga.alpha = misc;
+      ga.n = n;
+      ga.p0 = p0;
+      ga.S = Sp;
+      const int grid = (int)std::min<long long>((long long)Sp << g1.n_hi, gv_grid_max);
+      QST_HIP(qst::launch_gv_lo(ga, 5, grid, s));
+      qst::HiArgs hc{};
+      hc.src = WP;
+      hc.dst = gv;
+      hc.pc = pc_pat;
+      hc.D = D;
+      hc.R = 1;
+      hc.n = n;
+      hc.n_lo = g1.n_lo;
+      hc.n_hi = g1.n_hi;
+      hc.t = g1.t_adj;
+      hc.c = g1.c_adj;
+      hc.b0 = p0;
+      hc.S = Sp;
+      hc.first = p0 == 0;
+      hc.nsplit = std::min(g1.split_adj, split_of(h, g1, g1.c_adj, Sp));
+      hc.part = ws + L1.split;
+      Geometry gc = g1;
+      gc.t = g1.t_adj;
+      gc.c = g1.c_adj;
+      QST_HIP(qst::launch_stage_hi(gc, hc, true, s));
+      if (hc.nsplit > 1) QST_HIP(qst::launch_sum_splits(4, hc.part, hc.nsplit, D, gv, hc.first, s));
+    }
+    return QST_OK;
+  };
+
   // Atoms in complex128 for the low-rank term, and the unit weight of the G v products.
   QST_HIP(qst::launch_convert(inst->atoms, c64, A128, 0, (long long)R * D, 1.0, s));
   std::vector<double> alpha_h(R);
@@ -1961,22 +2110,10 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
     QST_HIP(qst::launch_combine(w, A128, R, D, coef, 1.0, 0, D, s));
     // eta_rho G q_j: adjoint pass with one unit-weight atom and sensitivity -g
     QST_HIP(qst::launch_convert(qj, 0, vin, c64, D, 1.0, s));
-    {
-      qst_instance one_inst = *inst;
-      one_inst.rank = 1;
-      one_inst.atoms = vin;
-      one_inst.weights = misc;
-      RunSpec rs{};
-      rs.in = &one_inst;
-      rs.path = path;
-      rs.loss_kind = QST_LOSS_NONE;
-      rs.grad_p = gneg;
-      rs.atom_grad = gv;
-      rs.adjoint = true;
-      rs.S_override = S1;
-      st = run_instance(h, rs, L1.pc, nullptr);
-      if (st != QST_OK) return st;
-    }
+    prof_outer_begin(h);
+    st = gv_product();
+    prof_outer_end(h);
+    if (st != QST_OK) return st;
     QST_HIP(qst::launch_axpy_c(w, 0, gv, c64, D, eta_rho, s));
     // a_j = Re <q_j, w>
     st = dots_host(qj, 1, w, 0, tmp);

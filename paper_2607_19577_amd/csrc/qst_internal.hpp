@@ -246,6 +246,26 @@ hipError_t launch_oc_decode(const OcInst* tab, int count, int blocks, int* flag,
 hipError_t launch_oc_finish(const OcInst* tab, int count, int sum_blocks, int rmax, bool rows, bool tangent,
                             hipStream_t st);
 
+// Grouped low stage of the G v products (one vector, FP32, Pauli settings, 14 low bits):
+// settings that share their high-bit codes (a pattern) share stage A's output X_P and
+// stage C's input W_P.  Item (pattern p0 + s, high index h): X_P's chunk h in registers,
+// W_P's chunk h = sum over the members b of the pattern of
+// L_b^dagger (alpha 2^-k_b g_b * L_b X_P) (L_b: the low-bit part of V_b, phases included).
+struct GvArgs {
+  const float2* X;      // [S][D] stage A output of patterns p0 .. p0 + S - 1
+  float2* W;            // [S][D]
+  const uint64_t* pc;   // [B] code words of the settings (all n qubits)
+  const int* perm;      // [B] the settings ordered by pattern
+  const int* goff;      // [P + 1] first position in perm of each pattern's members
+  const float* g;       // [B][D] sensitivities g_b
+  const double* alpha;  // [1] the vector's weight
+  int n, p0, S;
+};
+constexpr int kGvLoBits = 14;
+size_t gv_lds_bytes();
+int gv_blocks_per_cu(int logv);
+hipError_t launch_gv_lo(const GvArgs& a, int logv, int grid, hipStream_t st);
+
 // Register bits per thread of the low stage (2^logv values): 5, or 4 in the forward pass
 // over staged chunks of 2^12 and more outcomes (ranks up to 4: twice the wavefronts).
 constexpr int lo_logv_of(int n_lo, bool staged, bool adjoint) {
