@@ -51,7 +51,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-# ---------------------------------------------------------------- CPU baseline (oracle)
+# ---------------------------------------------------------------- CPU baseline leg (oracle)
+# Everything here runs the FP64 oracle on the host: the timed baseline and the references that
+# the GPU results' errors are taken against.  Nothing else in this file imports the oracle.
 _CPU = {}
 
 
@@ -59,6 +61,16 @@ def _cpu_init():
     from threadpoolctl import threadpool_limits
 
     threadpool_limits(1)
+
+
+def oracle_reference(atoms, w, s, f):
+    """The oracle's CE loss, atom gradient and weight gradient of a small sample instance, the
+    reference of the error checks (FP64, on the host)."""
+    from oracle import born
+
+    Lr, _, gar, gwr = born.forward_backward(np.asarray(atoms).astype(np.complex128), w, s,
+                                            np.asarray(f).astype(np.float64), born.LOSS_CE, 1e-8)
+    return Lr, gar, gwr
 
 
 def _cpu_probs(task):
@@ -155,6 +167,23 @@ def read_traffic(kernel_kind: str, workload: str):
     if d.get("source_hash") != kernel_source_hash():
         return None
     return float(d["bytes_per_launch"])
+
+
+def tile_extra(api, h, inst) -> dict:
+    """One backward of each MFMA tile path (FP16 and BF16 operands) on the step's instance after a
+    warm-up call of each (for profiling the tile passes)."""
+    import torch
+
+    grad = torch.empty_like(inst.atoms)
+    out = {}
+    for name, pth in (("tile_f16", api.PATH_TILE_F16), ("tile_bf16", api.PATH_TILE_BF16)):
+        api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=pth, out=[grad])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=pth, out=[grad])
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    return out
 
 
 def step_inputs(seed: int, n: int, R: int, B: int, R_true: int):
@@ -274,18 +303,20 @@ def solve_extra(api, h, dev, seed: int, slots: int = 100):
 VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak
 
 
-def onchip_extra(api, h, dev, seed: int, steps: int = 20, warmup: int = 3):
-    """The n=14, R=8, B=1000 workload (1e5 shots), where one (setting, atom) vector of 2^14
-    amplitudes fits a work-group and the whole rotation runs on chip: the same step as the
-    headline (decode, fused forward + adjoint with CE loss, weight gradient and tangent
-    projection, FP64 coefficient step), event-timed, with the two passes' times, the modelled HBM
-    bytes, a roofline against the FP32 vector peak (the path is bound by vector work and LDS
-    transposes, not HBM) and errors against the oracle on a sample of settings."""
+def config_extra(api, h, dev, seed: int, name: str = "n14_r8_b1000", steps: int = 20, warmup: int = 3,
+                 reference=None):
+    """One of the smaller configurations on one GPU: n=14, R=8, B=1000 (1e5 shots), where one
+    (setting, atom) vector of 2^14 amplitudes fits a work-group and the whole rotation runs on
+    chip (pass F with the atoms looped, pass A over slices of settings), or n=10, R=4, B=200
+    (1e4 shots), whose four atoms fit one work-group together (fused slices).  The step is the
+    headline's (decode, fused forward + adjoint with CE loss, weight gradient and tangent
+    projection, FP64 coefficient step), event-timed, with the passes' times, the modelled HBM
+    bytes, a roofline against the FP32 vector peak (these paths are bound by vector work and LDS
+    transposes, not HBM) and, with `reference` (the CPU baseline leg's oracle), errors on a
+    sample of settings."""
     import torch
 
-    from oracle import born
-
-    wl = WORKLOADS["n14_r8_b1000"]
+    wl = WORKLOADS[name]
     n, R, B, shots = wl["n"], wl["R"], wl["B"], wl["shots"]
     D = 1 << n
     rng = synth.make_rng(seed)
@@ -317,34 +348,48 @@ def onchip_extra(api, h, dev, seed: int, steps: int = 20, warmup: int = 3):
     h.profile(False)
     step_ms = float(np.median(ms))
     amps = B * R * D
-    tflops = 68.0 * amps / (step_ms * 1e-3) / 1e12  # the method's 68 flop per amplitude (fwd + adjoint)
-    # HBM bytes the step must move: frequencies read, 2^-k dL/dp written and read back (its re-reads by
-    # the other atom tiles of a slice come from L2), the slice partials written and summed, the atoms
-    # and the gradient
-    slices = max(1, min(256 // R, B // 16))
-    hbm = 3 * B * D * 4 + 2 * slices * R * D * 8 + 3 * R * D * 8
-    sample = [0, 333, 666, 999]
-    sub_s = s[sample]
-    sub_f = synth.porter_thomas_freqs(synth.make_rng(seed + 2), len(sample), D,
-                                      synth.dirichlet_weights(synth.make_rng(seed + 3), 4), shots)
-    sub = api.Instance(inst.atoms, inst.weights, torch.from_numpy(sub_s).to(dev), torch.from_numpy(sub_f).to(dev))
-    lt_s, ag_s, wg_s = api.qst_backward(h, [sub], loss=api.LOSS_CE, eps=1e-8)
-    torch.cuda.synchronize()
-    Lr, _, gar, gwr = born.forward_backward(atoms.astype(np.complex128), w, sub_s, sub_f.astype(np.float64),
-                                            born.LOSS_CE, 1e-8)
-    errs = {"loss": _relerr(float(lt_s[0]), Lr), "weight_grad": _relerr(wg_s[0].cpu().numpy(), gwr),
-            "atom_grad": _relerr(ag_s[0].cpu().numpy(), gar)}
-    return {"workload": f"n={n}, R={R}, B={B}, {shots} shots/setting, complex64, cross-entropy",
-            "ms_per_step": round(step_ms, 4), "amplitudes_per_s": amps / (step_ms * 1e-3),
-            "pass_ms_per_step": {"forward_atoms_looped": round(stages["hi_fwd"][1] / steps, 4),
-                                 "adjoint_slices": round(stages["lo_fused"][1] / steps, 4),
-                                 "sums_reductions_tangent": round(stages["reduce"][1] / steps, 4)},
-            "model_hbm_bytes_per_step": hbm, "model_GBps": round(hbm / (step_ms * 1e-3) / 1e9, 1),
-            "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
-                         "flops": "68 per (setting, atom) amplitude, the method's forward + adjoint"},
-            "errors_vs_oracle": {"settings": len(sample), **{k: float(f"{v:.3e}") for k, v in errs.items()},
-                                 "tol": 1e-5, "pass": all(v <= 1e-5 for v in errs.values())}}
+    # the method's flops per (setting, atom) amplitude, forward + adjoint: two rotations of
+    # 2 flop per element and qubit (a third of the qubits are Z, free), and 12 for |phi|^2, the
+    # atom sum, the weight-gradient term, the scaling by alpha g and the sum over settings
+    fpa = 4 * n + 12
+    tflops = fpa * amps / (step_ms * 1e-3) / 1e12
+    onchip = R * D > 16384
+    if onchip:
+        # frequencies read, 2^-k dL/dp written and read back (its re-reads by the other atom tiles
+        # of a slice come from L2), the slice partials written and summed, atoms and gradient
+        slices = max(1, min(256 // R, B // 16))
+        hbm = 3 * B * D * 4 + 2 * slices * R * D * 8 + 3 * R * D * 8
+        passes = {"forward_atoms_looped": round(stages["hi_fwd"][1] / steps, 4),
+                  "adjoint_slices": round(stages["lo_fused"][1] / steps, 4),
+                  "sums_reductions_tangent": round(stages["reduce"][1] / steps, 4)}
+    else:
+        # frequencies read, the slice partials written and summed, atoms and gradient
+        slices = max(1, B // 4)
+        hbm = B * D * 4 + 2 * slices * R * D * 8 + 3 * R * D * 8
+        passes = {"fused_slices": round(stages["lo_fused"][1] / steps, 4),
+                  "sums_reductions_tangent": round(stages["reduce"][1] / steps, 4)}
+    out = {"workload": f"n={n}, R={R}, B={B}, {shots} shots/setting, complex64, cross-entropy",
+           "kernels": "on chip, atoms looped" if onchip else "fused slices",
+           "ms_per_step": round(step_ms, 4), "amplitudes_per_s": amps / (step_ms * 1e-3),
+           "pass_ms_per_step": passes,
+           "model_hbm_bytes_per_step": hbm, "model_GBps": round(hbm / (step_ms * 1e-3) / 1e9, 1),
+           "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
+                        "flops": f"{fpa} per (setting, atom) amplitude, the method's forward + adjoint"}}
+    if reference is not None:
+        sample = [0, B // 3, (2 * B) // 3, B - 1]
+        sub_s = s[sample]
+        sub_f = synth.porter_thomas_freqs(synth.make_rng(seed + 2), len(sample), D,
+                                          synth.dirichlet_weights(synth.make_rng(seed + 3), 4), shots)
+        sub = api.Instance(inst.atoms, inst.weights, torch.from_numpy(sub_s).to(dev), torch.from_numpy(sub_f).to(dev))
+        lt_s, ag_s, wg_s = api.qst_backward(h, [sub], loss=api.LOSS_CE, eps=1e-8)
+        torch.cuda.synchronize()
+        Lr, gar, gwr = reference(atoms, w, sub_s, sub_f)
+        errs = {"loss": _relerr(float(lt_s[0]), Lr), "weight_grad": _relerr(wg_s[0].cpu().numpy(), gwr),
+                "atom_grad": _relerr(ag_s[0].cpu().numpy(), gar)}
+        out["errors_vs_oracle"] = {"settings": len(sample), **{k: float(f"{v:.3e}") for k, v in errs.items()},
+                                   "tol": 1e-5, "pass": all(v <= 1e-5 for v in errs.values())}
+    return out
 
 
 def uneven_batch_extra(api, h, dev, seed: int, reps: int = 5):
@@ -420,7 +465,7 @@ def main():
                          "BF16 intermediates (1e-2 variant)")
     ap.add_argument("--batch", type=int, default=0, help="settings per batch (0: library default or --autotune)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only a 1 GiB device copy (counter scale)")
-    ap.add_argument("--only", choices=["uneven64", "solve", "onchip", "refactor"], default=None,
+    ap.add_argument("--only", choices=["uneven64", "solve", "onchip", "cfg_n10", "refactor", "tile"], default=None,
                     help="run only one extra (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -441,7 +486,12 @@ def main():
         if args.only == "uneven64":
             res = uneven_batch_extra(api, h, dev, seed + 21)
         elif args.only == "onchip":
-            res = onchip_extra(api, h, dev, seed + 41)
+            res = config_extra(api, h, dev, seed + 41, reference=oracle_reference)
+        elif args.only == "cfg_n10":
+            res = config_extra(api, h, dev, seed + 51, name="n10_r4_b200", reference=oracle_reference)
+        elif args.only == "tile":
+            inst = step_instance(api, dev, seed, n, R, B, shots, wl["R_true"])
+            res = tile_extra(api, h, inst)
         elif args.only == "refactor":
             inst = step_instance(api, dev, seed, n, R, B, shots, wl["R_true"])
             res = refactor_extra(api, h, inst, seed + 11)
@@ -659,7 +709,9 @@ def main():
         extras.update(refactor_extra(api, h, inst, seed + 11))
 
     if not args.no_extras:
-        extras["n14_r8_b1000_onchip"] = onchip_extra(api, h, dev, seed + 41)
+        ref = None if args.no_cpu_baseline else oracle_reference
+        extras["n14_r8_b1000_onchip"] = config_extra(api, h, dev, seed + 41, reference=ref)
+        extras["n10_r4_b200_fused_slices"] = config_extra(api, h, dev, seed + 51, name="n10_r4_b200", reference=ref)
         extras["uneven64"] = uneven_batch_extra(api, h, dev, seed + 21)
         extras["solve"] = solve_extra(api, h, dev, seed + 31)
 
