@@ -631,17 +631,25 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
 #pragma unroll
     for (int i = 0; i < V; ++i) ax[i] = ay[i] = T(0);
     // Two register buffers take turns: the next setting's W tile is fetched into one
-    // while the other is transformed in place.
+    // while the other is transformed in place.  Every fetch is issued unconditionally (a
+    // setting past the split reads zeros through an empty buffer range): the number of
+    // loads in flight is then the same on every path into a use, so the compiler's wait
+    // there covers only the buffer in use.  A fetch under a condition made the waits
+    // assume the path without it and retire the prefetch too, every second setting.
     T px[V], py[V], qx[V], qy[V];
     float2 pe{0.f, 0.f}, qe{0.f, 0.f};
     auto issue = [&](int s, T (&bx)[V], T (&by)[V], float2& be) __attribute__((always_inline)) {
+      const bool valid = s < s_hi;
+      const int sv = valid ? s : s_lo;
       const rsrc_t rw = make_rsrc(
-          reinterpret_cast<const unsigned char*>(a.src) + ((long long)s * a.R * D + origin) * CBH, vbytes_h);
+          reinterpret_cast<const unsigned char*>(a.src) + ((long long)sv * a.R * D + origin) * CBH, valid ? vbytes_h : 0u);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         ld_cs<H16>(bx[i], by[i], rw, t0 * CBH, off0(i) * CBH);
       }
-      if constexpr (GEN) be = lane_e(s);
+      if constexpr (GEN) {
+        if (valid) be = lane_e(s);
+      }
     };
     auto body = [&](int s, T (&x)[V], T (&y)[V], const float2& e) __attribute__((always_inline)) {
       if constexpr (GEN) {
@@ -668,12 +676,12 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         ay[i] += y[i];
       }
     };
-    if (s_lo < s_hi) issue(s_lo, px, py, pe);
+    issue(s_lo, px, py, pe);
     for (int s = s_lo; s < s_hi; s += 2) {
-      if (s + 1 < s_hi) issue(s + 1, qx, qy, qe);
+      issue(s + 1, qx, qy, qe);
       body(s, px, py, pe);
       if (s + 1 < s_hi) {
-        if (s + 2 < s_hi) issue(s + 2, px, py, pe);
+        issue(s + 2, px, py, pe);
         body(s + 1, qx, qy, qe);
       }
     }
