@@ -102,12 +102,19 @@ typedef enum {
 
 /* One independent tomography instance (the arguments of the paper's problem
  * statement: atoms, weights, descriptor-level settings, observed frequencies).
- *   n_qubits  N, 1..20 (D = 2^N).  The staged kernels split the index bits into one
- *             low and one high pass of at most 2^14 amplitudes per tile and 2^10 rows,
- *             which covers N <= 20 at every rank; larger N would need a third pass over
- *             the high bits, not built, so larger N returns QST_ERR_SHAPE.
- *   rank      R, 1..16 (the atom count R_t; the low pass holds all R atoms of a chunk,
- *             R 2^(low bits) <= 2^14, so R <= 16 keeps at least ten low bits)
+ *   n_qubits  N, 1..30 (D = 2^N), with R 2^N times the bytes of a complex amplitude
+ *             below 4 GiB (one setting's vectors are addressed through one 32-bit buffer
+ *             range: N <= 24 at R = 16, N <= 28 at R = 1).  The staged kernels split the
+ *             index bits into a low pass (all R atoms of a chunk on chip, R 2^(low bits)
+ *             <= 2^14) and tile passes of 2^14 amplitudes with at most 2^10 rows over the
+ *             bits above it: one pass when there are at most ten such bits, else a middle
+ *             and a top pass (N up to the low bits + 20).  The plain and tile paths take
+ *             N <= 20 and R <= 16 (QST_ERR_UNSUPPORTED beyond).
+ *   rank      R, 1..256 (the atom count R_t).  Any such R runs when N >= 14 (staged
+ *             passes), when R 2^N <= 2^14 (the whole state of every atom in one
+ *             work-group), and for N = 11..13 on the FP32 path with Pauli settings and
+ *             dense frequencies (on chip, atoms in turn); other shapes (ranks above
+ *             2^(14-N) below 14 qubits) return QST_ERR_UNSUPPORTED.
  *   n_settings B >= 1
  *   atoms     [R][D] complex64 (complex128 for QST_PATH_BUTTERFLY_F64), 8-byte
  *             (16-byte) aligned
@@ -374,7 +381,8 @@ qst_status qst_state_error(qst_handle* h, int n_qubits, const void* atoms_a, con
  *   0 descriptor decode, 1 high-bit tile stage (forward), 2 fused low-bit stage,
  *   3 high-bit tile stage (adjoint, gradient accumulation), 4 reductions and
  *   epilogues, 5 other (reweight, refactor helpers, reference path), 6 one whole G v
- *   product of qst_refactor (its stages are then not counted under 1..4).
+ *   product of qst_refactor (its stages are then not counted under 1..4), 7 the middle
+ *   pass of the three-pass schedule (states with more than ten bits above the low stage).
  * qst_profile_read synchronises the stream and returns, for one kind, the number of
  * launches and their summed event-to-event milliseconds since the last reset
  * (reset != 0 clears every kind).  Enabling allocates events; launches made while

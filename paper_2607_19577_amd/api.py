@@ -56,7 +56,7 @@ class Handle:
     def profile(self, enable: bool = True) -> None:
         _lib.check(self.lib.qst_profile_enable(self.h, int(enable)), self.h)
 
-    STAGES = ("decode", "hi_fwd", "lo_fused", "hi_adj", "reduce", "other", "gv")
+    STAGES = ("decode", "hi_fwd", "lo_fused", "hi_adj", "reduce", "other", "gv", "mid")
 
     def profile_read(self, reset: bool = True) -> dict:
         """{stage: (launches, total_ms)} since the last reset (synchronises the stream)."""

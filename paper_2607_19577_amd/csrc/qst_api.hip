@@ -68,9 +68,12 @@ struct qst_handle {
 namespace {
 
 constexpr int G1 = 256;  // first-level reduction width
+// Largest rank: the low stage holds all R atoms of a chunk of at least 2^6 outcomes in one
+// work-group of at most 512 threads (R 2^6 <= 2^14), and the reweight kernel takes R <= 1024.
+constexpr int kMaxRank = 256;
 
-enum { PK_DECODE = 0, PK_HI_FWD = 1, PK_LO = 2, PK_HI_ADJ = 3, PK_REDUCE = 4, PK_OTHER = 5, PK_GV = 6 };
-constexpr int kProfKinds = 7;
+enum { PK_DECODE = 0, PK_HI_FWD = 1, PK_LO = 2, PK_HI_ADJ = 3, PK_REDUCE = 4, PK_OTHER = 5, PK_GV = 6, PK_MID = 7 };
+constexpr int kProfKinds = 8;
 
 hipEvent_t prof_event(qst_handle* h) {
   if (h->ev_next == h->ev_pool.size()) {
@@ -218,6 +221,20 @@ qst_status make_geometry(qst_handle* h, int n, int R, int B, qst_path path, Geom
   g.n_lo = n_lo;
   g.n_hi = n - n_lo;
   g.logv_lo = qst::lo_logv_of(n_lo, n_lo < n, true);
+  if (g.n_hi > 10 && elem == 4) {
+    // Three passes: the top bits for stages A and C, a middle pass for the rest; the split is
+    // as even as the tile shapes allow (longer contiguous rows for both tile passes).
+    const int lo_min = std::max(1, 14 - g.n_lo);  // a middle tile needs its 14 - rows columns below it
+    g.n_mid = std::min(10, std::max(lo_min, g.n_hi / 2));
+    const int top = g.n_hi - g.n_mid;
+    if (top < 1 || top > 10)
+      return set_err(h, QST_ERR_SHAPE,
+                     "n=" + std::to_string(n) + ", R=" + std::to_string(R) + ": the bits above the low stage need more than three passes");
+    g.c_mid = 14 - g.n_mid;
+    g.t = g.t_adj = 14;
+    g.c = g.c_adj = 14 - top;
+    return QST_OK;
+  }
   if (g.n_hi > 0) {
     if (elem != 4)
       return set_err(h, QST_ERR_UNSUPPORTED,
@@ -243,8 +260,17 @@ qst_status make_geometry(qst_handle* h, int n, int R, int B, qst_path path, Geom
   return QST_OK;
 }
 
+// The geometry as stages A and C see it: with a middle pass, their rows are the top
+// n_hi - n_mid bits, starting at bit n_lo + n_mid (the bits below them name the tile).
+Geometry top_view(const Geometry& g) {
+  Geometry t = g;
+  t.n_lo = g.n_lo + g.n_mid;
+  t.n_hi = g.n_hi - g.n_mid;
+  return t;
+}
+
 // Work-groups per tile of the high-bit stages: enough (tile, split) pairs for two per
-// CU, each split with at least 8 settings of the batch.
+// CU, each split with at least 8 settings of the batch.  (g: the stage's own view.)
 int split_of(const qst_handle* h, const Geometry& g, int c, int S) {
   if (g.n_hi == 0) return 1;
   const long long tiles = (long long)g.R << (g.n_lo - c);
@@ -255,7 +281,7 @@ int split_of(const qst_handle* h, const Geometry& g, int c, int S) {
 // Persistent low-stage grid for batches of S settings.
 void set_grid(qst_handle* h, Geometry& g, int S) {
   g.S = S;
-  g.split_adj = split_of(h, g, g.c_adj, S);
+  g.split_adj = split_of(h, top_view(g), g.c_adj, S);
   const long long chunks = (long long)S << g.n_hi;
   int per_cu = 1;
   if (h->device >= 0) {
@@ -358,9 +384,15 @@ void post_flag(qst_handle* h) {
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 qst_status validate_instance(qst_handle* h, const qst_instance& in, qst_path path, bool need_freqs) {
-  if (in.n_qubits < 1 || in.n_qubits > 20)
-    return set_err(h, QST_ERR_SHAPE, "n_qubits must be in 1..20 (got " + std::to_string(in.n_qubits) + ")");
-  if (in.rank < 1 || in.rank > 16) return set_err(h, QST_ERR_SHAPE, "rank must be in 1..16");
+  if (in.n_qubits < 1 || in.n_qubits > 30)
+    return set_err(h, QST_ERR_SHAPE, "n_qubits must be in 1..30 (got " + std::to_string(in.n_qubits) + ")");
+  if (in.rank < 1 || in.rank > kMaxRank)
+    return set_err(h, QST_ERR_SHAPE, "rank must be in 1.." + std::to_string(kMaxRank));
+  // one setting's R vectors are addressed through a 32-bit buffer range
+  if (((long long)in.rank << in.n_qubits) * (path == QST_PATH_BUTTERFLY_F64 ? 16 : 8) > 0xFFFFFFFFll)
+    return set_err(h, QST_ERR_SHAPE, "R * 2^n * (bytes per amplitude) must stay below 4 GiB");
+  if (pass_path(path) && (in.n_qubits > 20 || in.rank > 16))
+    return set_err(h, QST_ERR_UNSUPPORTED, "the plain and tile paths take n <= 20 and R <= 16");
   if (in.n_settings < 1) return set_err(h, QST_ERR_SHAPE, "n_settings must be >= 1");
   if (in.settings_per_batch < 0) return set_err(h, QST_ERR_SHAPE, "settings_per_batch must be >= 0");
   if (!in.atoms || !in.weights || !in.settings) return set_err(h, QST_ERR_INVALID_ARG, "null atoms/weights/settings");
@@ -527,6 +559,33 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
       prof_end(h);
       continue;
     }
+    // the middle pass of a three-pass schedule, in place on X (forward) or W (adjoint)
+    auto mid_pass = [&](void* buf, bool adj) -> qst_status {
+      qst::MidArgs ma{};
+      ma.buf = buf;
+      ma.pc = pc;
+      ma.um = um;
+      ma.D = g.D;
+      ma.R = g.R;
+      ma.n = g.n;
+      ma.row_lo = g.n_lo;
+      ma.rows = g.n_mid;
+      ma.t = 14;
+      ma.c = g.c_mid;
+      ma.b0 = b0;
+      ma.S = Sb;
+      // the middle tiles are named by every bit outside them (R 2^(n - 14) tiles): the view
+      // with those bits below the rows gives split_of that count
+      Geometry gm = g;
+      gm.n_lo = g.n - g.n_mid;
+      gm.n_hi = g.n_mid;
+      ma.nsplit = split_of(h, gm, g.c_mid, Sb);
+      prof_begin(h, PK_MID);
+      QST_HIP(qst::launch_stage_mid(g, ma, adj, s));
+      prof_end(h);
+      return QST_OK;
+    };
+    const Geometry gt = top_view(g);
     if (g.n_hi > 0) {
       qst::HiArgs ha{};
       ha.src = in.atoms;
@@ -536,17 +595,21 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
       ha.D = g.D;
       ha.R = g.R;
       ha.n = g.n;
-      ha.n_lo = g.n_lo;
-      ha.n_hi = g.n_hi;
+      ha.n_lo = gt.n_lo;
+      ha.n_hi = gt.n_hi;
       ha.t = g.t;
       ha.c = g.c;
       ha.b0 = b0;
       ha.S = Sb;
       ha.first = 0;
-      ha.nsplit = split_of(h, g, g.c, Sb);
+      ha.nsplit = split_of(h, gt, g.c, Sb);
       prof_begin(h, PK_HI_FWD);
-      QST_HIP(qst::launch_stage_hi(g, ha, false, s));
+      QST_HIP(qst::launch_stage_hi(gt, ha, false, s));
       prof_end(h);
+      if (g.n_mid > 0) {
+        st = mid_pass(X, false);
+        if (st != QST_OK) return st;
+      }
       la.src = X;
       la.src_set_stride = (long long)g.R * g.D;
     } else {
@@ -568,6 +631,10 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
     prof_end(h);
     if (rs.adjoint) {
       if (g.n_hi > 0) {
+        if (g.n_mid > 0) {
+          st = mid_pass(W, true);
+          if (st != QST_OK) return st;
+        }
         qst::HiArgs hc{};
         hc.src = W;
         hc.dst = rs.atom_grad;
@@ -576,17 +643,17 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
         hc.D = g.D;
         hc.R = g.R;
         hc.n = g.n;
-        hc.n_lo = g.n_lo;
-        hc.n_hi = g.n_hi;
+        hc.n_lo = gt.n_lo;
+        hc.n_hi = gt.n_hi;
         hc.t = g.t_adj;
         hc.c = g.c_adj;
         hc.b0 = b0;
         hc.S = Sb;
         hc.first = b0 == 0;
-        hc.nsplit = std::min(g.split_adj, split_of(h, g, g.c_adj, Sb));
+        hc.nsplit = std::min(g.split_adj, split_of(h, gt, g.c_adj, Sb));
         hc.part = ws + L.split;
         prof_begin(h, PK_HI_ADJ);
-        Geometry gc = g;
+        Geometry gc = gt;
         gc.t = g.t_adj;
         gc.c = g.c_adj;
         QST_HIP(qst::launch_stage_hi(gc, hc, true, s));
@@ -1305,7 +1372,7 @@ qst_status qst_profile_enable(qst_handle* h, int enable) {
 
 qst_status qst_profile_read(qst_handle* h, int kind, int64_t* launches, double* total_ms, int reset) {
   if (!h || !launches || !total_ms) return QST_ERR_INVALID_ARG;
-  if (kind < 0 || kind >= kProfKinds) return set_err(h, QST_ERR_INVALID_ARG, "kind must be in 0..6");
+  if (kind < 0 || kind >= kProfKinds) return set_err(h, QST_ERR_INVALID_ARG, "kind must be in 0..7");
   *launches = 0;
   *total_ms = 0.0;
   if (h->device < 0) return QST_OK;
@@ -1605,6 +1672,27 @@ static qst_status tune_policy(qst_handle* h, const qst_instance* inst, int n_ins
   return QST_OK;
 }
 
+// A kernel shape exists for the instance: the staged geometry, or else one of the instance-table
+// kinds for FP32 Pauli settings with dense frequencies -- fused slices (R 2^n <= 2^14) or the
+// on-chip passes (n = 11..14, rows of 16-byte aligned arrays: the instance's, and the call's when
+// `call_rows16`).
+static qst_status check_shape(qst_handle* h, const qst_instance& in, qst_path path, bool call_rows16 = true) {
+  Geometry g;
+  const qst_status st = make_geometry(h, in.n_qubits, in.rank, in.n_settings, path, g);
+  if (st == QST_OK) return st;
+  const bool table = resolve(path) == QST_PATH_BUTTERFLY_F32 && !in.unitaries && !in.freqs_rowptr &&
+                     in.settings_per_batch <= 0;
+  const bool fits = ((long long)in.rank << in.n_qubits) <= 16384;
+  auto a16 = [](const void* p) { return p == nullptr || aligned(p, 16); };
+  const bool oc = in.n_qubits >= 11 && in.n_qubits <= 14 && a16(in.atoms) && a16(in.freqs) && a16(in.probs_base) &&
+                  call_rows16;
+  if (table && (fits || oc)) {
+    h->last_error.clear();
+    return QST_OK;
+  }
+  return st;
+}
+
 qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_path path, int autotune) {
   qst_status st = common_checks(h, inst, n_inst, path);
   if (st != QST_OK) return st;
@@ -1612,8 +1700,7 @@ qst_status qst_plan(qst_handle* h, const qst_instance* inst, int n_inst, qst_pat
   for (int i = 0; i < n_inst; ++i) {
     st = validate_instance(h, inst[i], path, false);
     if (st != QST_OK) return st;
-    Geometry g;
-    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, path, g);
+    st = check_shape(h, inst[i], path);
     if (st != QST_OK) return st;
   }
   st = device_gate(h);
@@ -1672,8 +1759,7 @@ qst_status qst_forward(qst_handle* h, const qst_instance* inst, int n_inst, void
   for (int i = 0; i < n_inst; ++i) {
     st = validate_instance(h, inst[i], path, loss != nullptr);
     if (st != QST_OK) return st;
-    Geometry g;
-    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, path, g);
+    st = check_shape(h, inst[i], path, !probs || aligned(probs[i], 16));
     if (st != QST_OK) return st;
   }
   st = device_gate(h);
@@ -1716,8 +1802,7 @@ static qst_status backward_impl(qst_handle* h, const qst_instance* inst, int n_i
     const size_t ea = path == QST_PATH_BUTTERFLY_F64 ? 16 : 8;
     if (!aligned(atom_grad[i], ea)) return set_err(h, QST_ERR_ALIGN, "atom_grad misaligned");
     if (atom_grad[i] == inst[i].atoms) return set_err(h, QST_ERR_INVALID_ARG, "atom_grad aliases atoms");
-    Geometry g;
-    st = make_geometry(h, inst[i].n_qubits, inst[i].rank, inst[i].n_settings, path, g);
+    st = check_shape(h, inst[i], path, aligned(atom_grad[i], 16) && (!grad_p || aligned(grad_p[i], 16)));
     if (st != QST_OK) return st;
   }
   st = device_gate(h);
@@ -1921,7 +2006,7 @@ qst_status qst_refactor(qst_handle* h, const qst_instance* inst, qst_loss loss_k
   // G v with the settings grouped by their high codes (one vector, FP32, Pauli settings,
   // 14 low bits): pattern code words, member code words, member order, group starts and the
   // patterns' settings rows.
-  const bool grouped = gv_grouped_on() && c64 && !inst->unitaries && g1.n_hi > 0 && g1.n_lo == qst::kGvLoBits;
+  const bool grouped = gv_grouped_on() && c64 && !inst->unitaries && g1.n_hi > 0 && g1.n_mid == 0 && g1.n_lo == qst::kGvLoBits;
   const size_t off_grp = o;
   if (grouped) o = al256(o + (size_t)B * 8 * 2 + (size_t)B * 4 * 2 + 4 + (size_t)B * n + 256);
   st = ensure_ws(h, o);

@@ -17,8 +17,13 @@ namespace qst {
 struct Geometry {
   int n, R, B;
   long long D;
-  int n_lo, n_hi, t, c;
+  int n_lo, n_hi, t, c;  // n_hi: every index bit above the low stage
   int t_adj, c_adj;  // tile of the adjoint stage C (may differ from stage A's)
+  // Three-pass schedule (n_mid > 0): the bits above the low stage are more than one tile holds,
+  // so index bits [n_lo, n_lo + n_mid) get a middle pass of their own (in place on X and on W,
+  // tiles of 2^14 amplitudes with 2^c_mid contiguous columns) and stages A and C rotate the top
+  // n_hi - n_mid bits.
+  int n_mid, c_mid;
   int logv_lo;  // registers per thread in the low stage: 2^logv_lo
   int grid_lo;
   int S;
@@ -80,6 +85,17 @@ struct HiArgs {
   int nsplit;       // work-groups per tile, each over a contiguous share of the S settings
 };
 
+// Middle pass of the three-pass schedule: index bits [row_lo, row_lo + rows) of every (setting,
+// atom) vector of a batch, rotated in place (no phases).
+struct MidArgs {
+  void* buf;        // X (forward) or W (adjoint): [S][R][D]
+  const uint64_t* pc;
+  const float* um;  // general settings (else null), as in HiArgs
+  long long D;
+  int R, n, row_lo, rows, t, c, b0, S;
+  int nsplit;       // work-groups per tile, each over a contiguous share of the S settings
+};
+
 // Batches of small instances (whole state in one low-stage chunk, all settings in
 // one batch): one launch per step for up to kBatchMax instances, arguments by value.
 struct DecodeBatch {
@@ -132,6 +148,8 @@ hipError_t launch_decode(const uint8_t* settings, int B, int N, uint64_t* pc, in
 // g: geometry of the largest rank in the batch (LDS size, grid).
 hipError_t launch_stage_lo(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st);
 hipError_t launch_stage_hi(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st);
+// Middle pass (g: the instance's geometry; a.rows = g.n_mid, a.c = g.c_mid).
+hipError_t launch_stage_mid(const Geometry& g, const MidArgs& a, bool adjoint, hipStream_t st);
 hipError_t launch_sum_settings(const Geometry& g, const void* W, int S, void* grad, int first, hipStream_t st);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
 // Sparse frequencies: cptr[b * nh + h] = first non-zero of row b with outcome >= h * U

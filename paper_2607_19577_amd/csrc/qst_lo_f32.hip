@@ -23,6 +23,9 @@ hipError_t QST_LO_SUFFIX(launch_stage_lo)(const Geometry& g, const LoBatch& m, b
     return hipErrorInvalidValue;
   }
   switch (g.n_lo) {
+    case 6: return launch_lo_n<float, 6, false, QST_LO_H16>(g, m, adjoint, st);
+    case 7: return launch_lo_n<float, 7, false, QST_LO_H16>(g, m, adjoint, st);
+    case 8: return launch_lo_n<float, 8, false, QST_LO_H16>(g, m, adjoint, st);
     case 9: return launch_lo_n<float, 9, false, QST_LO_H16>(g, m, adjoint, st);
     case 10: return launch_lo_n<float, 10, false, QST_LO_H16>(g, m, adjoint, st);
     case 11: return launch_lo_n<float, 11, false, QST_LO_H16>(g, m, adjoint, st);
@@ -44,6 +47,9 @@ int QST_LO_SUFFIX(lo_occupancy)(const Geometry& g) {
     return 1;
   }
   switch (g.n_lo) {
+    case 6: return lo_occupancy_n<float, 6, false, QST_LO_H16>(g);
+    case 7: return lo_occupancy_n<float, 7, false, QST_LO_H16>(g);
+    case 8: return lo_occupancy_n<float, 8, false, QST_LO_H16>(g);
     case 9: return lo_occupancy_n<float, 9, false, QST_LO_H16>(g);
     case 10: return lo_occupancy_n<float, 10, false, QST_LO_H16>(g);
     case 11: return lo_occupancy_n<float, 11, false, QST_LO_H16>(g);

@@ -11,6 +11,9 @@ int lo_occupancy_gen_whole(const Geometry& g);
 hipError_t launch_stage_lo_gen(const Geometry& g, const LoBatch& m, bool adjoint, hipStream_t st) {
   if (g.n_hi == 0) return launch_stage_lo_gen_whole(g, m, adjoint, st);
   switch (g.n_lo) {
+    case 6: return launch_lo_n<float, 6, false, false, true>(g, m, adjoint, st);
+    case 7: return launch_lo_n<float, 7, false, false, true>(g, m, adjoint, st);
+    case 8: return launch_lo_n<float, 8, false, false, true>(g, m, adjoint, st);
     case 9: return launch_lo_n<float, 9, false, false, true>(g, m, adjoint, st);
     case 10: return launch_lo_n<float, 10, false, false, true>(g, m, adjoint, st);
     case 11: return launch_lo_n<float, 11, false, false, true>(g, m, adjoint, st);
@@ -24,6 +27,9 @@ hipError_t launch_stage_lo_gen(const Geometry& g, const LoBatch& m, bool adjoint
 int lo_occupancy_gen(const Geometry& g) {
   if (g.n_hi == 0) return lo_occupancy_gen_whole(g);
   switch (g.n_lo) {
+    case 6: return lo_occupancy_n<float, 6, false, false, true>(g);
+    case 7: return lo_occupancy_n<float, 7, false, false, true>(g);
+    case 8: return lo_occupancy_n<float, 8, false, false, true>(g);
     case 9: return lo_occupancy_n<float, 9, false, false, true>(g);
     case 10: return lo_occupancy_n<float, 10, false, false, true>(g);
     case 11: return lo_occupancy_n<float, 11, false, false, true>(g);

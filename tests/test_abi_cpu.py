@@ -59,9 +59,29 @@ def test_validation_paths(lib):
         # shape errors
         neg = _inst()
         neg.settings_per_batch = -1
-        for bad in (_inst(n=0), _inst(n=21), _inst(R=0), _inst(R=17), _inst(B=0), neg):
+        for bad in (_inst(n=0), _inst(n=31), _inst(R=0), _inst(R=257), _inst(B=0), neg,
+                    _inst(n=26, R=16), _inst(n=30, R=1)):  # the last two: one setting's vectors >= 4 GiB
             arr = (_lib.QstInstance * 1)(bad)
             assert lib.qst_forward(h, arr, 1, None, None, _lib.LOSS_NONE, 0.0, 0) == 2
+        # shapes the staged passes take: two passes (n=20, R=16), three (n=21, R=16;
+        # n=24, R=16; n=20, R=17; n=28, R=1) and the largest rank (n=18, R=256); they stop at the device gate
+        for okshape in ((20, 16), (21, 16), (24, 16), (20, 17), (28, 1), (18, 256), (14, 256), (6, 256)):
+            arr = (_lib.QstInstance * 1)(_inst(n=okshape[0], R=okshape[1]))
+            assert lib.qst_forward(h, arr, 1, None, None, _lib.LOSS_NONE, 0.0, 0) == 4, okshape
+            assert b"device" in lib.qst_last_error(h).lower(), (okshape, lib.qst_last_error(h))
+        # a rank above 2^(14-n) below 14 qubits has no staged shape: n = 11..13 runs on chip (FP32
+        # Pauli settings, dense frequencies), n = 10 not at all
+        for path, shape, ok in ((_lib.PATH_BUTTERFLY_F32, (12, 40), True), (_lib.PATH_BUTTERFLY_BF16, (12, 40), False),
+                                (_lib.PATH_BUTTERFLY_F32, (10, 32), False), (_lib.PATH_BUTTERFLY_BF16, (10, 32), False)):
+            arr = (_lib.QstInstance * 1)(_inst(n=shape[0], R=shape[1], atoms=0x10000, freqs=0x20000))
+            assert lib.qst_forward(h, arr, 1, None, None, _lib.LOSS_NONE, 0.0, path) == 4
+            msg = lib.qst_last_error(h)
+            assert (b"device" in msg.lower()) if ok else (b"tile-stage shapes" in msg), (path, shape, msg)
+        # the plain and tile paths stop at n = 20, R = 16
+        for bad in (_inst(n=21, R=4), _inst(n=12, R=32)):
+            arr = (_lib.QstInstance * 1)(bad)
+            assert lib.qst_forward(h, arr, 1, None, None, _lib.LOSS_NONE, 0.0, _lib.PATH_PLAIN_F32) == 4
+            assert b"plain and tile" in lib.qst_last_error(h)
         # null pointers
         for bad in (_inst(atoms=0), _inst(weights=0), _inst(settings=0)):
             arr = (_lib.QstInstance * 1)(bad)
