@@ -392,6 +392,61 @@ def config_extra(api, h, dev, seed: int, name: str = "n14_r8_b1000", steps: int 
     return out
 
 
+def threepass_extra(api, h, dev, seed: int, n: int = 22, R: int = 16, B: int = 500, shots: int = 1_000_000,
+                    steps: int = 3, warmup: int = 1) -> dict:
+    """A state above twenty qubits: n=22, R=16, B=500 (as many setting-atom amplitudes per step as
+    the headline's n=20, B=2000).  Twelve index bits lie above the low stage's ten, more than one
+    2^14-amplitude tile takes with at most 2^10 rows, so the staged path runs three passes: the
+    top tile stage, a middle tile pass in place on the setting batch's intermediates (on X after
+    the forward top stage and on W before the adjoint one), and the low stage.  The step is the
+    headline's, event-timed, with the stages' times and the modelled HBM bytes (the middle pass
+    reads and writes X and W once more each: 32 B per setting-atom amplitude in FP32)."""
+    import torch
+
+    D = 1 << n
+    inst = step_instance(api, dev, seed, n, R, B, shots, 4)
+    grad = torch.empty_like(inst.atoms)
+    def step():
+        _, _, wg = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, project_tangent=True, out=[grad],
+                                    path=api.PATH_BUTTERFLY_F32)
+        api.qst_reweight_simplex(h, inst.weights, wg[0], -0.5, 1e-3)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile(True)
+    h.profile_read(reset=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    stages = h.profile_read(reset=True)
+    h.profile(False)
+    step_ms = float(np.median(ms))
+    amps = B * R * D
+    ch, cb = 8, 8
+    # X written (stage A), read and written (middle), read (low stage); W written (low stage),
+    # read and written (middle), read (stage C); frequencies once per setting; atoms read by both
+    # top stages and the gradient read and written once per batch
+    batches = stages["lo_fused"][0] // steps
+    S = -(-B // batches)
+    hbm = 8 * B * R * D * ch + B * D * 4 + batches * 3 * R * D * cb
+    kinds = ("hi_fwd", "mid", "lo_fused", "hi_adj")
+    out = {"workload": f"n={n}, R={R}, B={B}, {shots} shots/setting, complex64, cross-entropy",
+           "passes": "three (top tile stage, middle tile pass, low stage)",
+           "settings_per_batch": S,
+           "ms_per_step": round(step_ms, 3), "amplitudes_per_s": amps / (step_ms * 1e-3),
+           "stage_ms_per_step": {k: round(stages[k][1] / steps, 3) for k in kinds + ("reduce",)},
+           "mid_launches_per_step": stages["mid"][0] // steps,
+           "model_hbm_bytes_per_step": hbm, "model_GBps": round(hbm / (step_ms * 1e-3) / 1e9, 1)}
+    del grad, inst
+    torch.cuda.empty_cache()
+    return out
+
+
 def uneven_batch_extra(api, h, dev, seed: int, reps: int = 5):
     """64 independent instances, n in 6..12, R in 1..8, B in 50..500 (fused CE backward with the
     tangent projection), planned with the autotuner: one call (one launch of each pass per class
@@ -465,7 +520,8 @@ def main():
                          "BF16 intermediates (1e-2 variant)")
     ap.add_argument("--batch", type=int, default=0, help="settings per batch (0: library default or --autotune)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only a 1 GiB device copy (counter scale)")
-    ap.add_argument("--only", choices=["uneven64", "solve", "onchip", "cfg_n10", "refactor", "tile"], default=None,
+    ap.add_argument("--only", choices=["uneven64", "solve", "onchip", "cfg_n10", "refactor", "tile",
+                                         "threepass"], default=None,
                     help="run only one extra (for profiling) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -489,6 +545,8 @@ def main():
             res = config_extra(api, h, dev, seed + 41, reference=oracle_reference)
         elif args.only == "cfg_n10":
             res = config_extra(api, h, dev, seed + 51, name="n10_r4_b200", reference=oracle_reference)
+        elif args.only == "threepass":
+            res = threepass_extra(api, h, dev, seed + 61)
         elif args.only == "tile":
             inst = step_instance(api, dev, seed, n, R, B, shots, wl["R_true"])
             res = tile_extra(api, h, inst)
@@ -714,6 +772,7 @@ def main():
         extras["n10_r4_b200_fused_slices"] = config_extra(api, h, dev, seed + 51, name="n10_r4_b200", reference=ref)
         extras["uneven64"] = uneven_batch_extra(api, h, dev, seed + 21)
         extras["solve"] = solve_extra(api, h, dev, seed + 31)
+        extras["n22_r16_b500_three_pass"] = threepass_extra(api, h, dev, seed + 61)
 
     out = {
         "metric": "fwd+adjoint atom-setting amplitudes/s",
