@@ -254,10 +254,17 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
     h_acc = 0.0;
   };
 
-  // Two register buffers take turns: chunk c + G is fetched into one while chunk c
-  // is transformed in place in the other.
-  T bpx[V], bpy[V], bpf[NPF], bqx[V], bqy[V], bqf[NPF];
-  auto issue = [&](int c, T (&bx)[V], T (&by)[V], T (&bf)[NPF]) __attribute__((always_inline)) {
+  // Two register buffers take turns: chunk c + G is fetched into one while chunk c is
+  // transformed in the other.  A buffer holds each amplitude's real and imaginary parts in
+  // adjacent registers, so every 64-bit load lands where the body reads it (with separate
+  // real and imaginary arrays the compiler moves the halves apart right after the load and
+  // has to wait for it there, which serialises the fetch with the work).  Every fetch is
+  // issued, also past the last chunk (then through an empty buffer range, which reads
+  // zeros): a fetch under a condition makes the compiler's waits cover it at once.
+  T bp[2 * V], bpf[NPF], bq[2 * V], bqf[NPF];
+  auto issue = [&](int c_in, T (&bb)[2 * V], T (&bf)[NPF]) __attribute__((always_inline)) {
+    const bool valid = c_in < m.total;
+    const int c = valid ? c_in : (m.total > 0 ? m.total - 1 : 0);
     const int k = inst_of(c);
     const LoArgs& a = m.a[k];
     const int cl = c - m.begin[k];
@@ -266,11 +273,11 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
     const unsigned char* sbase = reinterpret_cast<const unsigned char*>(a.src) +
                                  ((long long)s * a.src_set_stride + ((long long)h << N_LO)) * CBI;
     // threads of atoms beyond this instance's rank lie outside the extent: they read zeros
-    const rsrc_t rs = make_rsrc(sbase, extent(a, CBI));
+    const rsrc_t rs = make_rsrc(sbase, valid ? extent(a, CBI) : 0u);
     const uint32_t vo0 = voff(a, CBI);
 #pragma unroll
-    for (int i = 0; i < V; ++i) ld_cs<H16_IN>(bx[i], by[i], rs, vo0, (uint32_t)(i << LO0) * CBI);
-    if (a.grad_p != nullptr || (a.loss_kind != 2 && a.fidx == nullptr)) {
+    for (int i = 0; i < V; ++i) ld_cs<H16_IN>(bb[2 * i], bb[2 * i + 1], rs, vo0, (uint32_t)(i << LO0) * CBI);
+    if (valid && (a.grad_p != nullptr || (a.loss_kind != 2 && a.fidx == nullptr))) {
       const long long row = (long long)(a.b0 + s) * a.D + ((long long)h << N_LO);
 #pragma unroll
       for (int j = 0; j < NPF; ++j) {
@@ -284,8 +291,14 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
   // The body is inlined once per register buffer; every multiply-add in it is an
   // explicit fma and implicit contraction is off, so both copies round alike and a
   // chunk's results do not depend on which buffer (or which work-group) takes it.
-  auto body = [&](int c, T (&x)[V], T (&y)[V], const T (&bf)[NPF]) __attribute__((always_inline)) {
+  auto body = [&](int c, const T (&bb)[2 * V], const T (&bf)[NPF]) __attribute__((always_inline)) {
 #pragma clang fp contract(off)
+    T x[V], y[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      x[i] = bb[2 * i];
+      y[i] = bb[2 * i + 1];
+    }
     const int k = inst_of(c);
     if (k != cur) {
       if (cur >= 0) flush(cur);
@@ -453,14 +466,13 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
       if constexpr (!WL) __syncthreads();
     }
   };
+  issue(blockIdx.x, bp, bpf);
   for (int c = blockIdx.x; c < m.total; c += 2 * G) {
-    if (c == (int)blockIdx.x) issue(c, bpx, bpy, bpf);
-    if (c + G < m.total) issue(c + G, bqx, bqy, bqf);
-    body(c, bpx, bpy, bpf);
-    if (c + G < m.total) {
-      if (c + 2 * G < m.total) issue(c + 2 * G, bpx, bpy, bpf);
-      body(c + G, bqx, bqy, bqf);
-    }
+    issue(c + G, bq, bqf);
+    body(c, bp, bpf);
+    if (c + G >= m.total) break;
+    issue(c + 2 * G, bp, bpf);
+    body(c + G, bq, bqf);
   }
   if (cur >= 0) flush(cur);
   // Instances this work-group had no chunk of: zero partials, so every slot is defined.
