@@ -208,6 +208,9 @@ typedef struct {
   int32_t tile_bits_fwd;         /* kind 0 with high bits: tile bits of the forward tile stage */
   int32_t tile_bits_adj;         /* ... and of the adjoint tile stage (11..14, shape permitting) */
   int32_t values_per_thread_log2;/* kind 1: 4 (n = 13, 14) or 5                               */
+  int32_t w_row_bits;            /* kind 0 with high bits, two passes: the adjoint tile stage reads
+                                    rows of the low stage's output 2^w_row_bits elements apart
+                                    (tile columns..low bits; the low bits: plain [S][R][D] order) */
   int32_t tuned;                 /* out: 1 when the choice comes from qst_plan's timing        */
   double best_ms;                /* out: time of the chosen candidate on the timing slice      */
   double default_ms;             /* out: time of the library default on the same slice         */

@@ -171,8 +171,8 @@ def qst_plan(h: Handle, insts: Sequence[Instance], path: int = PATH_AUTO, autotu
     _lib.check(h.lib.qst_plan(h.h, arr, len(insts), path, int(autotune)), h.h)
 
 
-CHOICE_FIELDS = ("kind", "settings_per_batch", "tile_bits_fwd", "tile_bits_adj", "values_per_thread_log2", "tuned",
-                 "best_ms", "default_ms")
+CHOICE_FIELDS = ("kind", "settings_per_batch", "tile_bits_fwd", "tile_bits_adj", "values_per_thread_log2", "w_row_bits",
+                 "tuned", "best_ms", "default_ms")
 
 
 def qst_plan_choice(h: Handle, inst: Instance, path: int = PATH_AUTO, set_to: Optional[dict] = None) -> dict:

@@ -304,15 +304,38 @@ int env_batch() {
   return v;
 }
 
+// Layout of the low stage's output W for the adjoint tile stage (two passes): its tiles read
+// rows of 2^c_adj elements, 2^n_lo apart in plain order.  The low stage can store index bits
+// [wb, n_lo) of each chunk above the high bits instead (LoArgs::w_up = n_lo - wb), so those
+// rows lie 2^wb apart and neighbouring tiles share DRAM pages.  Measured at n=20, R=16,
+// B=2000 (rows of 16 elements), ms per step (low stage, adjoint tile stage): wb = 10 (plain)
+// 220.4 (113.1, 56.5); wb = 6 215.0 (114.1, 50.2); wb = 5 214.5 (114.3, 49.5); wb = 4 217.4
+// (118.0, 48.7).  With BF16 intermediates: 162.4, 158.1, 156.3, 156.9.  Default: wb = 5 when
+// the tile rows hold at most 32 elements, else plain.  The shape's choice (w_row_bits) or
+// QST_W_ROW_BITS (environment, read once) override it.
+int w_up_of(const qst_handle* h, const Geometry& g, qst_path path) {
+  static const int env = [] {
+    const char* e = std::getenv("QST_W_ROW_BITS");
+    return e ? std::atoi(e) : 0;
+  }();
+  const int dflt = g.c_adj <= 5 ? std::min(5, g.n_lo) : g.n_lo;
+  int wb = env > 0 ? env : dflt;
+  if (const qst_choice* c = find_choice(h, g.n, g.R, g.B, path))
+    if (c->w_row_bits > 0) wb = c->w_row_bits;
+  if (wb < g.c_adj || wb > g.n_lo) wb = dflt;
+  return g.n_lo - wb;
+}
+
 int default_S(const Geometry& g) {
   if (env_batch() > 0) return std::min(env_batch(), g.B);
   const long long per = (long long)g.R * g.D * 2 * g.elem;
-  long long s = (8ll << 30) / std::max(per, 1ll);
+  long long s = (16ll << 30) / std::max(per, 1ll);
   if (s < 1) s = 1;
   if (s > g.B) s = g.B;
-  // X and W hold S settings each (8 GiB each at most, S = 64 at n=20, R=16).  Larger
+  // X and W hold S settings each (16 GiB each at most, S = 128 at n=20, R=16).  Larger
   // batches amortise the psi read and the gradient update and need fewer launches
-  // (measured at n=20, R=16, B=2000: S = 4 -> 337, 16 -> 253, 64 -> 229 ms per step).
+  // (measured at n=20, R=16, B=2000: S = 4 -> 337, 16 -> 253, 64 -> 220, 96 -> 218.7,
+  // 128 -> 218.1 ms per step).
   return (int)s;
 }
 
@@ -527,6 +550,8 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   la.B = g.B;
   la.loss_kind = rs.grad_p ? 2 : (int)rs.loss_kind;
   la.eps = rs.eps;
+  // the W layout only matters between the low stage and the adjoint top stage
+  la.w_up = (rs.adjoint && g.n_hi > 0 && g.n_mid == 0 && !pass_path(path)) ? w_up_of(h, g, path) : 0;
 
   for (int b0 = 0; b0 < g.B; b0 += S) {
     const int Sb = std::min(S, g.B - b0);
@@ -652,6 +677,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
         hc.first = b0 == 0;
         hc.nsplit = std::min(g.split_adj, split_of(h, gt, g.c_adj, Sb));
         hc.part = ws + L.split;
+        hc.w_up = la.w_up;
         prof_begin(h, PK_HI_ADJ);
         Geometry gc = gt;
         gc.t = g.t_adj;
@@ -1580,12 +1606,19 @@ static qst_status tune_shape(qst_handle* h, const qst_instance& in0, qst_path pa
   if (staged_ok && g.n_hi > 0) {
     const size_t per = (size_t)R * ((size_t)1 << n) * 2 * elem_of(path);
     for (int S : {16, 32, 64, 128})
-      if (S <= ins[0].n_settings && (size_t)S * per <= (8ull << 30)) cand(0, S, 0, 0, 0);
+      if (S <= ins[0].n_settings && (size_t)S * per <= (16ull << 30)) cand(0, S, 0, 0, 0);
     for (int t : {13, 12})
       if (t < 14 && g.n_hi <= (t == 13 ? 3 : 2) && t - g.n_hi <= g.n_lo) {
         cand(0, 0, t, 0, 0);
         cand(0, 0, 0, t, 0);
       }
+    // the layout of W between the low stage and the adjoint tile stage (two passes)
+    if (g.n_mid == 0)
+      for (int wb : {5, 6, g.n_lo})
+        if (wb >= g.c_adj && wb <= g.n_lo && (wb != g.n_lo || wb > 6)) {
+          cand(0, 0, 0, 0, 0);
+          cands.back().w_row_bits = wb;
+        }
   }
   // workspace: the largest candidate, then the outputs
   size_t need = 0;
@@ -1733,7 +1766,8 @@ qst_status qst_plan_choice(qst_handle* h, const qst_instance* inst, qst_path pat
   const auto key = shape_key(inst->n_qubits, inst->rank, inst->n_settings, path);
   if (set) {
     if (choice->kind < -1 || choice->kind > 2 || choice->settings_per_batch < 0 || choice->tile_bits_fwd < 0 ||
-        choice->tile_bits_adj < 0 || choice->values_per_thread_log2 < 0)
+        choice->tile_bits_adj < 0 || choice->values_per_thread_log2 < 0 || choice->w_row_bits < 0 ||
+        choice->w_row_bits > 14)
       return set_err(h, QST_ERR_INVALID_ARG, "choice fields out of range");
     h->choices[key] = *choice;
     return QST_OK;

@@ -458,11 +458,15 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
       if constexpr (PHASE && !GEN) apply_phase<true, LOGV>(x, y, pos0, ym, [](int i) { return (uint32_t)(i << LO0); });
       if constexpr (PHASE && GEN)
         apply_gphase<true, LOGV>(x, y, pos0, a.n, [](int i) { return (uint32_t)(i << LO0); }, PhaseLoad{um});
-      unsigned char* dbase = reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + ((long long)h << N_LO)) * CBO;
-      const rsrc_t rd = make_rsrc(dbase, extent(a, CBO));
-      const uint32_t vo0 = voff(a, CBO);
+      // W position of chunk element l: index bits [wb, N_LO) go above the high bits
+      const int wb = N_LO - a.w_up;
+      auto wpos = [&](uint32_t l) { return ((l >> wb) << (a.n_hi + wb)) | (l & ((1u << wb) - 1u)); };
+      unsigned char* dbase = reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + ((long long)h << wb)) * CBO;
+      // atoms beyond the instance's rank fall outside the range: their stores are dropped
+      const rsrc_t rd = make_rsrc(dbase, (uint32_t)(((long long)a.R * D - ((long long)h << wb)) * CBO));
+      const uint32_t vo0 = (uint32_t)(((long long)atom * D + wpos(pos0)) * CBO);
 #pragma unroll
-      for (int i = 0; i < V; ++i) st_cs<H16>(x[i], y[i], rd, vo0, (uint32_t)(i << LO0) * CBO);
+      for (int i = 0; i < V; ++i) st_cs<H16>(x[i], y[i], rd, vo0, wpos((uint32_t)(i << LO0)) * CBO);
       if constexpr (!WL) __syncthreads();
     }
   };
@@ -584,6 +588,14 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   const uint32_t vof = tf * CB;
   auto off0 = [=](int i) { return tile_off((uint32_t)i << LO0, C, n_lo); };
   auto offf = [=](int i) { return tile_off((uint32_t)i << LOF, C, n_lo); };
+  // The adjoint reads W, whose rows lie 2^wb elements apart (the low stage moved index bits
+  // [wb, n_lo) above the high bits; wb = n_lo: plain layout, wb >= C).
+  const int wb = n_lo - a.w_up;
+  const uint32_t cphys = ((cbase >> wb) << (a.n_hi + wb)) | (cbase & ((1u << wb) - 1u));
+  const long long origin_w = (long long)r * D + cphys;
+  const uint32_t vbytes_w = (uint32_t)((D - cphys) * CBH);
+  const uint32_t t0w = tile_off(lay_pos<LOGV>(tid, 0, LO0), C, wb);
+  auto off0w = [=](int i) { return tile_off((uint32_t)i << LO0, C, wb); };
 
   // General settings: lane q of every wavefront holds the phase e_q of the setting
   // (fetched one setting ahead) for the per-element phase.
@@ -654,10 +666,10 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
       const bool valid = s < s_hi;
       const int sv = valid ? s : s_lo;
       const rsrc_t rw = make_rsrc(
-          reinterpret_cast<const unsigned char*>(a.src) + ((long long)sv * a.R * D + origin) * CBH, valid ? vbytes_h : 0u);
+          reinterpret_cast<const unsigned char*>(a.src) + ((long long)sv * a.R * D + origin_w) * CBH, valid ? vbytes_w : 0u);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        ld_cs<H16>(bx[i], by[i], rw, t0 * CBH, off0(i) * CBH);
+        ld_cs<H16>(bx[i], by[i], rw, t0w * CBH, off0w(i) * CBH);
       }
       if constexpr (GEN) {
         if (valid) be = lane_e(s);
@@ -688,12 +700,16 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         ay[i] += y[i];
       }
     };
-    issue(s_lo, px, py, pe);
+    // General settings keep the conditional fetches: their per-lane phases make the
+    // unconditional form run out of registers (160 spilled), which costs far more than
+    // the early waits.
+    constexpr bool UNCOND = !GEN;
+    if (UNCOND || s_lo < s_hi) issue(s_lo, px, py, pe);
     for (int s = s_lo; s < s_hi; s += 2) {
-      issue(s + 1, qx, qy, qe);
+      if (UNCOND || s + 1 < s_hi) issue(s + 1, qx, qy, qe);
       body(s, px, py, pe);
       if (s + 1 < s_hi) {
-        issue(s + 2, px, py, pe);
+        if (UNCOND || s + 2 < s_hi) issue(s + 2, px, py, pe);
         body(s + 1, qx, qy, qe);
       }
     }

@@ -7,7 +7,9 @@
 * A later handle on the same device reuses the process-wide choice without timing again.
 * Every kind of kernels pinned at a shape where all apply matches the oracle.
 * Tuning a multi-instance call keeps a routing policy; the tuned call matches the oracle and
-  replays from a graph bit for bit."""
+  replays from a graph bit for bit.
+* The order in which the low stage stores its output for the adjoint tile stage (w_row_bits)
+  moves values, not sums: every order gives the same bits."""
 import numpy as np
 import pytest
 import torch
@@ -50,7 +52,7 @@ def test_autotune_one_shape(tmp_path):
         assert c["best_ms"] <= c["default_ms"], c
         a = _bw(h1, [inst])
         pin = {k: c[k] for k in ("kind", "settings_per_batch", "tile_bits_fwd", "tile_bits_adj",
-                                 "values_per_thread_log2")}
+                                 "values_per_thread_log2", "w_row_bits")}
         got = api.qst_plan_choice(h2, inst, set_to=pin)
         assert got["kind"] == c["kind"] and got["tuned"] == 0
         b = _bw(h2, [inst])
@@ -116,3 +118,38 @@ def test_autotune_call_policy_and_graph():
             assert torch.equal(out[0], ref[0]), rep
             for x, y in zip(out[1], ref[1]):
                 assert torch.equal(x, y), rep
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16", "general"])
+def test_w_layouts_give_the_same_bits(kind):
+    """n=19, R=16 (adjoint tiles of 2^9 rows by 32 columns, so the low stage's output order
+    matters), three batches of 16 settings: the plain order (rows 2^10 apart) and rows 2^5
+    (the default here), 2^6 and 2^8 apart give equal losses, probabilities and gradients, on
+    the FP32 path, with BF16 intermediates and with general local settings."""
+    from paper_2607_19577_amd import api
+    import synth
+
+    rng = synth.make_rng(1250)
+    n, R, B = 19, 16, 40
+    atoms = synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64)
+    w = synth.dirichlet_weights(rng, R)
+    s = synth.random_general_settings(rng, B, n, 2) if kind == "general" else synth.random_settings(rng, B, n)
+    f = synth.porter_thomas_freqs(rng, B, 1 << n, synth.dirichlet_weights(rng, 3), 20000)
+    unitaries = torch.from_numpy(synth.haar_unitaries_2x2(rng, 2)).to(DEV) if kind == "general" else None
+    inst = api.Instance(torch.from_numpy(atoms).to(DEV), torch.from_numpy(w).to(DEV), torch.from_numpy(s).to(DEV),
+                        torch.from_numpy(f).to(DEV), unitaries=unitaries)
+    path = api.PATH_BUTTERFLY_BF16 if kind == "bf16" else api.PATH_BUTTERFLY_F32
+    ref = None
+    for wb in (10, 5, 6, 8):
+        print("w_row_bits", wb, kind, flush=True)
+        with api.Handle(0) as h:
+            api.qst_plan_choice(h, inst, path=path, set_to={"kind": 0, "settings_per_batch": 16, "w_row_bits": wb})
+            probs, _ = api.qst_forward(h, [inst], want_probs=True, path=path)
+            got = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=path)
+            torch.cuda.synchronize()
+            out = (probs[0].cpu(), float(got[0][0]), got[1][0].cpu(), got[2][0].cpu())
+        if ref is None:
+            ref = out
+            continue
+        assert torch.equal(out[0], ref[0]) and out[1] == ref[1], wb
+        assert torch.equal(out[2], ref[2]) and torch.equal(out[3], ref[3]), wb
