@@ -211,6 +211,8 @@ typedef struct {
   int32_t w_row_bits;            /* kind 0 with high bits, two passes: the adjoint tile stage reads
                                     rows of the low stage's output 2^w_row_bits elements apart
                                     (tile columns..low bits; the low bits: plain [S][R][D] order) */
+  int32_t x_row_bits;            /* ... and the forward tile stage writes its rows for the low
+                                    stage 2^x_row_bits elements apart (likewise)               */
   int32_t tuned;                 /* out: 1 when the choice comes from qst_plan's timing        */
   double best_ms;                /* out: time of the chosen candidate on the timing slice      */
   double default_ms;             /* out: time of the library default on the same slice         */

@@ -76,6 +76,7 @@ class QstChoice(ctypes.Structure):
         ("tile_bits_adj", ctypes.c_int32),
         ("values_per_thread_log2", ctypes.c_int32),
         ("w_row_bits", ctypes.c_int32),
+        ("x_row_bits", ctypes.c_int32),
         ("tuned", ctypes.c_int32),
         ("best_ms", ctypes.c_double),
         ("default_ms", ctypes.c_double),

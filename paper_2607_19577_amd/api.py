@@ -172,7 +172,7 @@ def qst_plan(h: Handle, insts: Sequence[Instance], path: int = PATH_AUTO, autotu
 
 
 CHOICE_FIELDS = ("kind", "settings_per_batch", "tile_bits_fwd", "tile_bits_adj", "values_per_thread_log2", "w_row_bits",
-                 "tuned", "best_ms", "default_ms")
+                 "x_row_bits", "tuned", "best_ms", "default_ms")
 
 
 def qst_plan_choice(h: Handle, inst: Instance, path: int = PATH_AUTO, set_to: Optional[dict] = None) -> dict:

@@ -326,6 +326,25 @@ int w_up_of(const qst_handle* h, const Geometry& g, qst_path path) {
   return g.n_lo - wb;
 }
 
+// Order of X between the forward tile stage and the low stage, as for W (LoArgs::x_up).
+// Measured at n=20, R=16, B=2000 (rows of 16 elements), ms per step (forward tile stage, low
+// stage): xb = 10 (plain) 215.1 (49.9, 115.2); xb = 6 213.9 (50.0, 114.0); xb = 5 229.0
+// (52.3, 126.3); xb = 4 225.7 (51.0, 124.5).  With BF16 intermediates: 155.0, 151.6, 170.1,
+// 191.8.  Default: xb = 6 when the tile rows hold at most 32 elements, else plain; the
+// shape's choice (x_row_bits) or QST_X_ROW_BITS (environment, read once) override it.
+int x_up_of(const qst_handle* h, const Geometry& g, qst_path path) {
+  static const int env = [] {
+    const char* e = std::getenv("QST_X_ROW_BITS");
+    return e ? std::atoi(e) : 0;
+  }();
+  const int dflt = g.c <= 5 ? std::min(6, g.n_lo) : g.n_lo;
+  int xb = env > 0 ? env : dflt;
+  if (const qst_choice* c = find_choice(h, g.n, g.R, g.B, path))
+    if (c->x_row_bits > 0) xb = c->x_row_bits;
+  if (xb < g.c || xb > g.n_lo) xb = dflt;
+  return g.n_lo - xb;
+}
+
 int default_S(const Geometry& g) {
   if (env_batch() > 0) return std::min(env_batch(), g.B);
   const long long per = (long long)g.R * g.D * 2 * g.elem;
@@ -552,6 +571,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   la.eps = rs.eps;
   // the W layout only matters between the low stage and the adjoint top stage
   la.w_up = (rs.adjoint && g.n_hi > 0 && g.n_mid == 0 && !pass_path(path)) ? w_up_of(h, g, path) : 0;
+  la.x_up = (g.n_hi > 0 && g.n_mid == 0 && !pass_path(path)) ? x_up_of(h, g, path) : 0;
 
   for (int b0 = 0; b0 < g.B; b0 += S) {
     const int Sb = std::min(S, g.B - b0);
@@ -628,6 +648,7 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
       ha.S = Sb;
       ha.first = 0;
       ha.nsplit = split_of(h, gt, g.c, Sb);
+      ha.w_up = la.x_up;
       prof_begin(h, PK_HI_FWD);
       QST_HIP(qst::launch_stage_hi(gt, ha, false, s));
       prof_end(h);
@@ -1612,13 +1633,19 @@ static qst_status tune_shape(qst_handle* h, const qst_instance& in0, qst_path pa
         cand(0, 0, t, 0, 0);
         cand(0, 0, 0, t, 0);
       }
-    // the layout of W between the low stage and the adjoint tile stage (two passes)
-    if (g.n_mid == 0)
+    // the orders of X and W between the tile stages and the low stage (two passes)
+    if (g.n_mid == 0) {
       for (int wb : {5, 6, g.n_lo})
         if (wb >= g.c_adj && wb <= g.n_lo && (wb != g.n_lo || wb > 6)) {
           cand(0, 0, 0, 0, 0);
           cands.back().w_row_bits = wb;
         }
+      for (int xb : {6, g.n_lo})
+        if (xb >= g.c && xb <= g.n_lo && (xb != g.n_lo || xb > 6)) {
+          cand(0, 0, 0, 0, 0);
+          cands.back().x_row_bits = xb;
+        }
+    }
   }
   // workspace: the largest candidate, then the outputs
   size_t need = 0;
@@ -1767,7 +1794,7 @@ qst_status qst_plan_choice(qst_handle* h, const qst_instance* inst, qst_path pat
   if (set) {
     if (choice->kind < -1 || choice->kind > 2 || choice->settings_per_batch < 0 || choice->tile_bits_fwd < 0 ||
         choice->tile_bits_adj < 0 || choice->values_per_thread_log2 < 0 || choice->w_row_bits < 0 ||
-        choice->w_row_bits > 14)
+        choice->w_row_bits > 14 || choice->x_row_bits < 0 || choice->x_row_bits > 14)
       return set_err(h, QST_ERR_INVALID_ARG, "choice fields out of range");
     h->choices[key] = *choice;
     return QST_OK;

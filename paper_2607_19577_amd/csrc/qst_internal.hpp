@@ -59,10 +59,10 @@ struct LoArgs {
   int R, n, n_lo, n_hi, log_ta, b0, B;
   int loss_kind;
   double eps;
-  // W layout: the top w_up index bits of a chunk ([n_lo - w_up, n_lo)) are stored above the
-  // high bits, so that the adjoint tile stage reads rows 2^(n_lo - w_up) elements apart
-  // (0: plain [S][R][D] order)
-  int w_up;
+  // Orders of X (input) and W (output): the top x_up (w_up) index bits of a chunk are stored
+  // above the high bits, so that the tile stages' rows lie 2^(n_lo - x_up) (2^(n_lo - w_up))
+  // elements apart (0: plain [S][R][D] order)
+  int x_up, w_up;
 };
 
 // One launch of the low stage over several instances of the same low-bit count:
@@ -87,7 +87,7 @@ struct HiArgs {
   long long D;
   int R, n, n_lo, n_hi, t, c, b0, S, first;
   int nsplit;       // work-groups per tile, each over a contiguous share of the S settings
-  int w_up;         // adjoint: the layout of W written by the low stage (LoArgs::w_up)
+  int w_up;         // forward: the order of X (LoArgs::x_up); adjoint: of W (LoArgs::w_up)
 };
 
 // Middle pass of the three-pass schedule: index bits [row_lo, row_lo + rows) of every (setting,

@@ -212,9 +212,8 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
     while (k + 1 < m.count && c >= m.begin[k + 1]) ++k;
     return k;
   };
-  // Buffer extent of one chunk (all atoms of the instance) and this thread's offset.
+  // Buffer extent of one chunk (all atoms of the instance) in plain order.
   auto extent = [&](const LoArgs& a, uint32_t cb) { return (uint32_t)(((long long)(a.R - 1) * a.D + U) * cb); };
-  auto voff = [&](const LoArgs& a, uint32_t cb) { return (uint32_t)(((long long)atom * a.D + pos0) * cb); };
 
   double loss_acc = 0.0, h_acc = 0.0;
   T al_cur = T(0);         // this thread's atom weight in the current instance
@@ -270,13 +269,18 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
     const int cl = c - m.begin[k];
     const int s = cl >> a.n_hi;
     const int h = cl & ((1 << a.n_hi) - 1);
+    // X position of chunk element l: index bits [xb, N_LO) above the high bits (xb = N_LO:
+    // plain order, and always when the input is the atoms)
+    const int xb = N_LO - a.x_up;
+    auto xpos = [&](uint32_t l) { return ((l >> xb) << (a.n_hi + xb)) | (l & ((1u << xb) - 1u)); };
     const unsigned char* sbase = reinterpret_cast<const unsigned char*>(a.src) +
-                                 ((long long)s * a.src_set_stride + ((long long)h << N_LO)) * CBI;
+                                 ((long long)s * a.src_set_stride + ((long long)h << xb)) * CBI;
     // threads of atoms beyond this instance's rank lie outside the extent: they read zeros
-    const rsrc_t rs = make_rsrc(sbase, valid ? extent(a, CBI) : 0u);
-    const uint32_t vo0 = voff(a, CBI);
+    const uint32_t ext = a.x_up ? (uint32_t)(((long long)a.R * a.D - ((long long)h << xb)) * CBI) : extent(a, CBI);
+    const rsrc_t rs = make_rsrc(sbase, valid ? ext : 0u);
+    const uint32_t vo0 = (uint32_t)(((long long)atom * a.D + xpos(pos0)) * CBI);
 #pragma unroll
-    for (int i = 0; i < V; ++i) ld_cs<H16_IN>(bb[2 * i], bb[2 * i + 1], rs, vo0, (uint32_t)(i << LO0) * CBI);
+    for (int i = 0; i < V; ++i) ld_cs<H16_IN>(bb[2 * i], bb[2 * i + 1], rs, vo0, xpos((uint32_t)(i << LO0)) * CBI);
     if (valid && (a.grad_p != nullptr || (a.loss_kind != 2 && a.fidx == nullptr))) {
       const long long row = (long long)(a.b0 + s) * a.D + ((long long)h << N_LO);
 #pragma unroll
@@ -463,7 +467,8 @@ __global__ __launch_bounds__((lo_max_threads<N_LO, PHASE, ADJ>())) void k_stage_
       auto wpos = [&](uint32_t l) { return ((l >> wb) << (a.n_hi + wb)) | (l & ((1u << wb) - 1u)); };
       unsigned char* dbase = reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + ((long long)h << wb)) * CBO;
       // atoms beyond the instance's rank fall outside the range: their stores are dropped
-      const rsrc_t rd = make_rsrc(dbase, (uint32_t)(((long long)a.R * D - ((long long)h << wb)) * CBO));
+      const rsrc_t rd =
+          make_rsrc(dbase, a.w_up ? (uint32_t)(((long long)a.R * D - ((long long)h << wb)) * CBO) : extent(a, CBO));
       const uint32_t vo0 = (uint32_t)(((long long)atom * D + wpos(pos0)) * CBO);
 #pragma unroll
       for (int i = 0; i < V; ++i) st_cs<H16>(x[i], y[i], rd, vo0, wpos((uint32_t)(i << LO0)) * CBO);
@@ -588,14 +593,17 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   const uint32_t vof = tf * CB;
   auto off0 = [=](int i) { return tile_off((uint32_t)i << LO0, C, n_lo); };
   auto offf = [=](int i) { return tile_off((uint32_t)i << LOF, C, n_lo); };
-  // The adjoint reads W, whose rows lie 2^wb elements apart (the low stage moved index bits
-  // [wb, n_lo) above the high bits; wb = n_lo: plain layout, wb >= C).
+  // X (forward output) and W (adjoint input) may be stored with index bits [wb, n_lo) above
+  // the high bits (the low stage uses the same order), so a tile's rows lie 2^wb elements
+  // apart (wb = n_lo: plain layout, wb >= C).
   const int wb = n_lo - a.w_up;
   const uint32_t cphys = ((cbase >> wb) << (a.n_hi + wb)) | (cbase & ((1u << wb) - 1u));
   const long long origin_w = (long long)r * D + cphys;
   const uint32_t vbytes_w = (uint32_t)((D - cphys) * CBH);
   const uint32_t t0w = tile_off(lay_pos<LOGV>(tid, 0, LO0), C, wb);
+  const uint32_t tfw = tile_off(lay_pos<LOGV>(tid, 0, LOF), C, wb);
   auto off0w = [=](int i) { return tile_off((uint32_t)i << LO0, C, wb); };
+  auto offfw = [=](int i) { return tile_off((uint32_t)i << LOF, C, wb); };
 
   // General settings: lane q of every wavefront holds the phase e_q of the setting
   // (fetched one setting ahead) for the per-element phase.
@@ -646,9 +654,9 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
         }
       }
       const rsrc_t rx =
-          make_rsrc(reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + origin) * CBH, vbytes_h);
+          make_rsrc(reinterpret_cast<unsigned char*>(a.dst) + ((long long)s * a.R * D + origin_w) * CBH, vbytes_w);
 #pragma unroll
-      for (int i = 0; i < V; ++i) st_cs<H16>(x[i], y[i], rx, tf * CBH, offf(i) * CBH);
+      for (int i = 0; i < V; ++i) st_cs<H16>(x[i], y[i], rx, tfw * CBH, offfw(i) * CBH);
     }
   } else {
     T ax[V], ay[V];

@@ -52,7 +52,7 @@ def test_autotune_one_shape(tmp_path):
         assert c["best_ms"] <= c["default_ms"], c
         a = _bw(h1, [inst])
         pin = {k: c[k] for k in ("kind", "settings_per_batch", "tile_bits_fwd", "tile_bits_adj",
-                                 "values_per_thread_log2", "w_row_bits")}
+                                 "values_per_thread_log2", "w_row_bits", "x_row_bits")}
         got = api.qst_plan_choice(h2, inst, set_to=pin)
         assert got["kind"] == c["kind"] and got["tuned"] == 0
         b = _bw(h2, [inst])
@@ -122,10 +122,11 @@ def test_autotune_call_policy_and_graph():
 
 @pytest.mark.parametrize("kind", ["f32", "bf16", "general"])
 def test_w_layouts_give_the_same_bits(kind):
-    """n=19, R=16 (adjoint tiles of 2^9 rows by 32 columns, so the low stage's output order
-    matters), three batches of 16 settings: the plain order (rows 2^10 apart) and rows 2^5
-    (the default here), 2^6 and 2^8 apart give equal losses, probabilities and gradients, on
-    the FP32 path, with BF16 intermediates and with general local settings."""
+    """n=19, R=16 (tiles of 2^9 rows by 32 columns, so the orders of X and W matter), three
+    batches of 16 settings: W in plain order (rows 2^10 apart) and with rows 2^5 (the default
+    here), 2^6 and 2^8 apart, each with X in plain order or rows 2^6 (the default) or 2^5
+    apart, give equal losses, probabilities and gradients, on the FP32 path, with BF16
+    intermediates and with general local settings."""
     from paper_2607_19577_amd import api
     import synth
 
@@ -140,10 +141,11 @@ def test_w_layouts_give_the_same_bits(kind):
                         torch.from_numpy(f).to(DEV), unitaries=unitaries)
     path = api.PATH_BUTTERFLY_BF16 if kind == "bf16" else api.PATH_BUTTERFLY_F32
     ref = None
-    for wb in (10, 5, 6, 8):
-        print("w_row_bits", wb, kind, flush=True)
+    for wb, xb in ((10, 10), (5, 6), (6, 5), (8, 10)):
+        print("w_row_bits", wb, "x_row_bits", xb, kind, flush=True)
         with api.Handle(0) as h:
-            api.qst_plan_choice(h, inst, path=path, set_to={"kind": 0, "settings_per_batch": 16, "w_row_bits": wb})
+            api.qst_plan_choice(h, inst, path=path, set_to={"kind": 0, "settings_per_batch": 16, "w_row_bits": wb,
+                                                           "x_row_bits": xb})
             probs, _ = api.qst_forward(h, [inst], want_probs=True, path=path)
             got = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=path)
             torch.cuda.synchronize()
