@@ -14,7 +14,7 @@ LIB = os.path.join(PKG, "libqst.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["qst_lo_gen_whole.hip", "qst_lo_gen.hip", "qst_kernels.hip", "qst_lo_f32.hip", "qst_lo_h16.hip",
-           "qst_lo_f64.hip", "qst_hi.hip", "qst_hi_gen.hip", "qst_mid.hip", "qst_tile.hip", "qst_onchip.hip", "qst_gv.hip", "qst_api.hip",
+           "qst_lo_f64.hip", "qst_hi.hip", "qst_hi_gen.hip", "qst_mid.hip", "qst_lo2.hip", "qst_tile.hip", "qst_onchip.hip", "qst_gv.hip", "qst_api.hip",
            "qst_solve.hip"]
 
 # Packed-FP32 instructions are kept out of the device code on purpose.

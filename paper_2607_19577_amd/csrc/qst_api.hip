@@ -285,9 +285,11 @@ void set_grid(qst_handle* h, Geometry& g, int S) {
   const long long chunks = (long long)S << g.n_hi;
   int per_cu = 1;
   if (h->device >= 0) {
-    const auto key = std::make_tuple(g.n_lo, (g.n_hi > 0 ? 1 : 0) | (g.h16 ? 2 : 0) | (g.gen ? 4 : 0), g.R, g.elem);
+    const auto key = std::make_tuple(g.n_lo, (g.n_hi > 0 ? 1 : 0) | (g.h16 ? 2 : 0) | (g.gen ? 4 : 0) | (g.lo2 ? 8 : 0),
+                                     g.R, g.elem);
     auto it = h->occupancy.find(key);
-    if (it == h->occupancy.end()) it = h->occupancy.emplace(key, qst::lo_blocks_per_cu(g)).first;
+    if (it == h->occupancy.end())
+      it = h->occupancy.emplace(key, g.lo2 ? qst::lo2_occupancy(g) : qst::lo_blocks_per_cu(g)).first;
     per_cu = it->second;
   }
   const long long resident = (long long)h->num_cu * per_cu;
@@ -480,6 +482,23 @@ struct RunSpec {
 void mark(Geometry& g, const qst_instance& in) {
   g.gen = in.unitaries != nullptr;
   g.sparse = in.freqs_rowptr != nullptr;
+  // More than ten bits above the low stage: with Pauli settings and dense data the low stage
+  // takes n - 10 bits with its atoms looped (two sweeps over X), which keeps two tile passes
+  // and moves 24 B per (setting, atom) amplitude less than a middle pass (section on the
+  // three-pass schedule).  QST_LO2=0 (environment, read once) keeps the middle pass.
+  static const bool lo2_on = [] {
+    const char* e = std::getenv("QST_LO2");
+    return !(e && std::atoi(e) == 0);
+  }();
+  if (lo2_on && g.n_mid > 0 && !g.gen && !g.sparse && g.elem == 4 && g.n - 10 >= 10 && g.n - 10 <= 14) {
+    g.lo2 = true;
+    g.n_lo = g.n - 10;
+    g.n_hi = 10;
+    g.n_mid = g.c_mid = 0;
+    g.t = g.t_adj = 14;
+    g.c = g.c_adj = 4;
+    g.logv_lo = g.n_lo <= 10 ? 4 : 5;
+  }
 }
 
 // Settings per batch of one instance: the override, else the caller's choice, the
@@ -570,8 +589,9 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
   la.loss_kind = rs.grad_p ? 2 : (int)rs.loss_kind;
   la.eps = rs.eps;
   // the W layout only matters between the low stage and the adjoint top stage
-  la.w_up = (rs.adjoint && g.n_hi > 0 && g.n_mid == 0 && !pass_path(path)) ? w_up_of(h, g, path) : 0;
-  la.x_up = (g.n_hi > 0 && g.n_mid == 0 && !pass_path(path)) ? x_up_of(h, g, path) : 0;
+  const bool reorder = g.n_hi > 0 && g.n_mid == 0 && !pass_path(path);
+  la.w_up = (rs.adjoint && reorder) ? w_up_of(h, g, path) : 0;
+  la.x_up = reorder ? x_up_of(h, g, path) : 0;
 
   for (int b0 = 0; b0 < g.B; b0 += S) {
     const int Sb = std::min(S, g.B - b0);
@@ -664,7 +684,9 @@ qst_status run_instance(qst_handle* h, const RunSpec& rs, size_t ws_base = 0, si
     }
     la.dst = W;
     prof_begin(h, PK_LO);
-    {
+    if (g.lo2) {
+      QST_HIP(qst::launch_stage_lo2(g, la, rs.adjoint, s));
+    } else {
       qst::LoBatch lb{};
       lb.count = 1;
       lb.total = la.nchunks;

@@ -32,6 +32,9 @@ struct Geometry {
   bool h16;      // the setting-batch intermediates X and W are stored in BF16
   bool gen;      // general local settings: a rotation and a phase per (setting, qubit) from the decode
   bool sparse;   // sparse (CSR) frequencies: chunk pointers in the workspace
+  // Two-sweep low stage (lo2): the low stage takes n_lo = n - 10 bits with the atoms looped in
+  // one work-group (X read twice), so the bits above it fit one tile pass (n_mid = 0).
+  bool lo2;
 };
 
 struct LoArgs {
@@ -155,6 +158,11 @@ hipError_t launch_stage_lo(const Geometry& g, const LoBatch& m, bool adjoint, hi
 hipError_t launch_stage_hi(const Geometry& g, const HiArgs& a, bool adjoint, hipStream_t st);
 // Middle pass (g: the instance's geometry; a.rows = g.n_mid, a.c = g.c_mid).
 hipError_t launch_stage_mid(const Geometry& g, const MidArgs& a, bool adjoint, hipStream_t st);
+// Two-sweep low stage (qst_lo2.hip): n_lo 10..14, FP32 Pauli settings, dense data, X and W in
+// FP32 or BF16 (g.h16).
+hipError_t launch_stage_lo2(const Geometry& g, const LoArgs& a, bool adjoint, hipStream_t st);
+int lo2_occupancy(const Geometry& g);
+size_t lo2_lds_bytes(const Geometry& g);
 hipError_t launch_sum_settings(const Geometry& g, const void* W, int S, void* grad, int first, hipStream_t st);
 hipError_t launch_fill(void* p, size_t bytes, hipStream_t st);
 // Sparse frequencies: cptr[b * nh + h] = first non-zero of row b with outcome >= h * U

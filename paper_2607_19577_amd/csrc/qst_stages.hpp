@@ -586,7 +586,6 @@ __global__ __launch_bounds__(512) void k_stage_hi(const HiArgs a) {
   const long long origin = (long long)r * D + cbase;
   const uint32_t vbytes = (uint32_t)((D - cbase) * CB);
   constexpr uint32_t CBH = H16 ? 4u : CB;  // bytes per complex of X and W
-  const uint32_t vbytes_h = (uint32_t)((D - cbase) * CBH);
   const uint32_t t0 = tile_off(lay_pos<LOGV>(tid, 0, LO0), C, n_lo);
   const uint32_t tf = tile_off(lay_pos<LOGV>(tid, 0, LOF), C, n_lo);
   const uint32_t vo0 = t0 * CB;

@@ -1,10 +1,11 @@
-"""GPU parity of the three-pass schedule and of ranks above 16.
+"""GPU parity of the schedules for more than ten bits above the low stage, and of ranks above 16.
 
 When the index bits above the low stage are more than one tile of 2^14 amplitudes holds with at
-most 2^10 rows, the staged path adds a middle tile pass (in place on the setting-batch
-intermediates X and W) between the top tile stage and the low stage: n = 21 at R = 16, or
-n = 20 at R = 17..32 (nine low bits, eleven above them).  Ranks above 16 also reach the low
-stage with six to eight low bits, the on-chip passes (n = 11..14) and the fused slices
+most 2^10 rows (n = 21 at R = 16, or n = 20 at R = 17..32, whose low stage takes nine bits), the
+staged path either gives the low stage n - 10 bits with its atoms looped in one work-group (two
+sweeps over X; Pauli settings and dense data) or adds a middle tile pass in place on the
+setting-batch intermediates X and W (general settings, sparse data).  Ranks above 16 also reach
+the low stage with six to eight low bits, the on-chip passes (n = 11..14) and the fused slices
 (R 2^n <= 2^14).  Every case is compared with the FP64 oracle (norm-wise and element-wise
 scaled, 1e-5 in FP32, 1e-2 with BF16 intermediates) on the same seeded inputs, or, where the
 oracle would take minutes, with closed forms of the adjoint that hold at any size.
@@ -74,10 +75,33 @@ def _check(got, ref, tol, what):
 
 
 def test_three_pass_n20_r17_against_the_oracle(h):
-    """n=20, R=17: nine low bits, a middle pass of five bits and a top pass of six; two settings
-    in two batches of one (the middle pass on X and on W once per batch)."""
+    """n=20, R=17 (nine low bits would leave eleven above them): the two-sweep low stage over ten
+    bits with dense frequencies, and the middle pass (five bits, top pass of six) with the same
+    frequencies in CSR form; two settings in two batches of one."""
     case = _case(9101, 20, 17, 2)
-    _check(_gpu(h, _inst(case, S=1)), _oracle(case), TOL32, "n=20 R=17 three passes")
+    ref = _oracle(case)
+    _check(_gpu(h, _inst(case, S=1)), ref, TOL32, "n=20 R=17 two-sweep low stage")
+    _check(_gpu(h, _sparse(_inst(case, S=1))), ref, TOL32, "n=20 R=17 middle pass (sparse data)")
+
+
+def _sparse(inst):
+    rp, ix, vals = synth.dense_to_csr(inst.freqs.cpu().numpy())
+    inst.freqs = None
+    inst.freqs_csr = (torch.from_numpy(rp).to(DEV), torch.from_numpy(ix).to(DEV), torch.from_numpy(vals).to(DEV))
+    return inst
+
+
+def test_two_sweep_low_stage_equals_the_middle_pass(h):
+    """n=21, R=16, six settings in batches of four: the two-sweep low stage (dense data) and the
+    middle pass (the same data in CSR form) give the same loss, probabilities and gradients to
+    rounding, in FP32 and with BF16 intermediates (1e-2)."""
+    from paper_2607_19577_amd import api
+
+    case = _case(9105, 21, 16, 6, shots=20_000)
+    for path, tol in ((api.PATH_BUTTERFLY_F32, TOL32), (api.PATH_BUTTERFLY_BF16, 1e-2)):
+        a = _gpu(h, _inst(case, S=4), path=path)
+        b = _gpu(h, _sparse(_inst(case, S=4)), path=api.PATH_BUTTERFLY_F32)
+        _check(a, b, tol, f"two sweeps vs middle pass, path {path}")
 
 
 def test_three_pass_equals_two_pass_with_a_zero_weight_atom(h):
@@ -99,9 +123,10 @@ def test_three_pass_equals_two_pass_with_a_zero_weight_atom(h):
     assert np.abs(ga17[16]).max() == 0.0
 
 
-@pytest.mark.parametrize("n,R", [(21, 16), (22, 4)])
+@pytest.mark.parametrize("n,R", [(21, 16), (22, 4), (22, 16), (23, 8), (24, 2)])
 def test_beyond_twenty_qubits_closed_forms(h, n, R):
-    """n=21 (three passes at R=16) and n=22 (two at R=4): sensitivity g = 1 gives alpha_r B psi_r
+    """n=21..24: the two-sweep low stage over 11 to 14 bits (R = 16, 16, 8, 2) and two plain tile
+    passes (n=22 at R=4): sensitivity g = 1 gives alpha_r B psi_r
     and B ||psi_r||^2 (V^dagger V = 1 per setting); g = (-1)^{u_j} gives alpha_r sum_b
     sigma^(j)_{s_bj} psi_r for qubit j, one in each pass; a Z-only setting's probabilities are
     sum_r alpha_r |psi_r|^2; and every setting's probabilities sum to sum_r alpha_r ||psi_r||^2."""

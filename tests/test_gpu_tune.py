@@ -120,18 +120,19 @@ def test_autotune_call_policy_and_graph():
                 assert torch.equal(x, y), rep
 
 
-@pytest.mark.parametrize("kind", ["f32", "bf16", "general"])
-def test_w_layouts_give_the_same_bits(kind):
-    """n=19, R=16 (tiles of 2^9 rows by 32 columns, so the orders of X and W matter), three
-    batches of 16 settings: W in plain order (rows 2^10 apart) and with rows 2^5 (the default
+@pytest.mark.parametrize("n,kind", [(19, "f32"), (19, "bf16"), (19, "general"), (21, "f32"), (21, "bf16")])
+def test_w_layouts_give_the_same_bits(n, kind):
+    """n=19, R=16 (tiles of 2^9 rows by 32 columns, so the orders of X and W matter) and n=21,
+    R=16 (the two-sweep low stage over eleven bits, tiles of 2^10 rows by 16 columns), three
+    batches of 16 settings: W in plain order (rows 2^n_lo apart) and with rows 2^5 (the default
     here), 2^6 and 2^8 apart, each with X in plain order or rows 2^6 (the default) or 2^5
     apart, give equal losses, probabilities and gradients, on the FP32 path, with BF16
     intermediates and with general local settings."""
     from paper_2607_19577_amd import api
     import synth
 
-    rng = synth.make_rng(1250)
-    n, R, B = 19, 16, 40
+    rng = synth.make_rng(1250 + n)
+    R, B = 16, 40
     atoms = synth.haar_atoms(rng, R, 1 << n, dtype=np.complex64)
     w = synth.dirichlet_weights(rng, R)
     s = synth.random_general_settings(rng, B, n, 2) if kind == "general" else synth.random_settings(rng, B, n)
@@ -141,7 +142,8 @@ def test_w_layouts_give_the_same_bits(kind):
                         torch.from_numpy(f).to(DEV), unitaries=unitaries)
     path = api.PATH_BUTTERFLY_BF16 if kind == "bf16" else api.PATH_BUTTERFLY_F32
     ref = None
-    for wb, xb in ((10, 10), (5, 6), (6, 5), (8, 10)):
+    n_lo = n - 10 if n > 20 else 10
+    for wb, xb in ((n_lo, n_lo), (5, 6), (6, 5), (8, n_lo)):
         print("w_row_bits", wb, "x_row_bits", xb, kind, flush=True)
         with api.Handle(0) as h:
             api.qst_plan_choice(h, inst, path=path, set_to={"kind": 0, "settings_per_batch": 16, "w_row_bits": wb,
