@@ -107,9 +107,11 @@ typedef enum {
  *             range: N <= 24 at R = 16, N <= 28 at R = 1).  The staged kernels split the
  *             index bits into a low pass (all R atoms of a chunk on chip, R 2^(low bits)
  *             <= 2^14) and tile passes of 2^14 amplitudes with at most 2^10 rows over the
- *             bits above it: one pass when there are at most ten such bits, else a middle
- *             and a top pass (N up to the low bits + 20).  The plain and tile paths take
- *             N <= 20 and R <= 16 (QST_ERR_UNSUPPORTED beyond).
+ *             bits above it: one pass when there are at most ten such bits; else, with Pauli
+ *             settings and dense frequencies, a low pass over N - 10 bits that takes the
+ *             atoms in turn (N <= 24), otherwise a middle and a top pass (N up to the low
+ *             bits + 20).  The plain and tile paths take N <= 20 and R <= 16
+ *             (QST_ERR_UNSUPPORTED beyond).
  *   rank      R, 1..256 (the atom count R_t).  Any such R runs when N >= 14 (staged
  *             passes), when R 2^N <= 2^14 (the whole state of every atom in one
  *             work-group), and for N = 11..13 on the FP32 path with Pauli settings and
