@@ -49,12 +49,13 @@ def _inst(case, S=0, unitaries=None):
                         settings_per_batch=S, unitaries=unitaries)
 
 
-def _gpu(h, inst, path=None):
+def _gpu(h, inst, path=None, loss=None):
     from paper_2607_19577_amd import api
 
     path = api.PATH_BUTTERFLY_F32 if path is None else path
+    loss = api.LOSS_CE if loss is None else loss
     probs, _ = api.qst_forward(h, [inst], want_probs=True, path=path)
-    lt, ag, wg = api.qst_backward(h, [inst], loss=api.LOSS_CE, eps=1e-8, path=path)
+    lt, ag, wg = api.qst_backward(h, [inst], loss=loss, eps=1e-8, path=path)
     torch.cuda.synchronize()
     return float(lt[0]), probs[0].cpu().numpy(), ag[0].cpu().numpy(), wg[0].cpu().numpy()
 
@@ -94,14 +95,22 @@ def _sparse(inst):
 def test_two_sweep_low_stage_equals_the_middle_pass(h):
     """n=21, R=16, six settings in batches of four: the two-sweep low stage (dense data) and the
     middle pass (the same data in CSR form) give the same loss, probabilities and gradients to
-    rounding, in FP32 and with BF16 intermediates (1e-2)."""
+    rounding, for the CE and LS losses, in FP32 and (CE) with BF16 intermediates (1e-2)."""
     from paper_2607_19577_amd import api
 
     case = _case(9105, 21, 16, 6, shots=20_000)
-    for path, tol in ((api.PATH_BUTTERFLY_F32, TOL32), (api.PATH_BUTTERFLY_BF16, 1e-2)):
-        a = _gpu(h, _inst(case, S=4), path=path)
-        b = _gpu(h, _sparse(_inst(case, S=4)), path=api.PATH_BUTTERFLY_F32)
-        _check(a, b, tol, f"two sweeps vs middle pass, path {path}")
+    for path, tol, loss in ((api.PATH_BUTTERFLY_F32, TOL32, api.LOSS_CE), (api.PATH_BUTTERFLY_F32, TOL32, api.LOSS_LS),
+                            (api.PATH_BUTTERFLY_BF16, 1e-2, api.LOSS_CE)):
+        a = _gpu(h, _inst(case, S=4), path=path, loss=loss)
+        b = _gpu(h, _sparse(_inst(case, S=4)), path=api.PATH_BUTTERFLY_F32, loss=loss)
+        _check(a, b, tol, f"two sweeps vs middle pass, path {path}, loss {loss}")
+
+
+def test_two_sweep_low_stage_n22_against_the_oracle(h):
+    """n=22, R=16: the two-sweep low stage over twelve bits (128 threads per atom), one setting,
+    against the oracle."""
+    case = _case(9106, 22, 16, 1)
+    _check(_gpu(h, _inst(case)), _oracle(case), TOL32, "n=22 R=16 two-sweep low stage")
 
 
 def test_three_pass_equals_two_pass_with_a_zero_weight_atom(h):
