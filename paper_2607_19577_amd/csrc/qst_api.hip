@@ -94,8 +94,7 @@ bool capturing(hipStream_t st) {
 void prof_begin(qst_handle* h, int kind) {
   if (!h->prof || h->static_ws || h->prof_outer || capturing(h->stream)) return;
   hipEvent_t e = prof_event(h);
-  if (!e) return;
-  hipEventRecord(e, h->stream);
+  if (!e || hipEventRecord(e, h->stream) != hipSuccess) return;
   h->open_kind = kind;
   h->open_ev = e;
 }
@@ -103,8 +102,7 @@ void prof_begin(qst_handle* h, int kind) {
 void prof_end(qst_handle* h) {
   if (!h->prof || h->static_ws || h->prof_outer || h->open_kind < 0 || capturing(h->stream)) return;
   hipEvent_t e = prof_event(h);
-  if (!e) return;
-  hipEventRecord(e, h->stream);
+  if (!e || hipEventRecord(e, h->stream) != hipSuccess) return;
   h->marks.push_back({h->open_kind, h->open_ev, e});
   h->open_kind = -1;
 }
@@ -411,7 +409,8 @@ qst_status check_flag(qst_handle* h) {
   if (*h->hflag) {
     const int f = *h->hflag;
     *h->hflag = 0;
-    qst::launch_fill(h->dflag, sizeof(int), h->stream);
+    if (qst::launch_fill(h->dflag, sizeof(int), h->stream) != hipSuccess)
+      return set_err(h, QST_ERR_DEVICE, "clearing the device flag failed");
     std::string msg;
     if (f & 1) msg = "a setting held a code outside the Pauli codes and the unitary table";
     if (f & 2) msg += std::string(msg.empty() ? "" : "; ") + "a unitary table entry was not unitary to 1e-6";
@@ -422,8 +421,10 @@ qst_status check_flag(qst_handle* h) {
 
 void post_flag(qst_handle* h) {
   if (capturing(h->stream)) return;
-  hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
-  hipEventRecord(h->flag_ev, h->stream);
+  // a flag that cannot be fetched is not reported (the call's own status covers the failure)
+  if (hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipEventRecord(h->flag_ev, h->stream) != hipSuccess)
+    return;
   h->flag_pending = true;
 }
 
@@ -1496,8 +1497,13 @@ qst_status qst_create(int device, void* hip_stream, qst_handle** out) {
     return QST_ERR_DEVICE;
   }
   *h->hflag = 0;
-  hipMemset(h->dflag, 0, sizeof(int));
-  hipDeviceSynchronize();
+  if (hipMemset(h->dflag, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(h->dflag);
+    (void)hipHostFree(h->hflag);
+    (void)hipEventDestroy(h->flag_ev);
+    delete h;
+    return QST_ERR_DEVICE;
+  }
   if (scratch_address(device, &h->static_scratch) != hipSuccess) h->static_scratch = nullptr;
   *out = h;
   return QST_OK;
@@ -1509,14 +1515,15 @@ qst_status qst_destroy(qst_handle* h) {
     delete h;
     return QST_OK;
   }
-  hipSetDevice(h->device);
-  hipStreamSynchronize(h->stream);
-  if (h->ws) hipFree(h->ws);
-  for (void* p : h->retired) hipFree(p);
-  if (h->dflag) hipFree(h->dflag);
-  if (h->hflag) hipHostFree(h->hflag);
-  if (h->flag_ev) hipEventDestroy(h->flag_ev);
-  for (hipEvent_t e : h->ev_pool) hipEventDestroy(e);
+  // teardown: every release is attempted; their statuses are not reported
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->ws) (void)hipFree(h->ws);
+  for (void* p : h->retired) (void)hipFree(p);
+  if (h->dflag) (void)hipFree(h->dflag);
+  if (h->hflag) (void)hipHostFree(h->hflag);
+  if (h->flag_ev) (void)hipEventDestroy(h->flag_ev);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
   return QST_OK;
 }
@@ -1554,26 +1561,25 @@ static std::map<std::pair<std::string, uint64_t>, std::pair<int, int>> g_policy_
 struct Timer {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   Timer() {
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    if (hipEventCreate(&e0) != hipSuccess) e0 = nullptr;
+    if (hipEventCreate(&e1) != hipSuccess) e1 = nullptr;
   }
   ~Timer() {
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
   }
 };
 
 // Median time (ms) of the call, or a negative value when it fails (the candidate is then skipped).
 static double time_call(qst_handle* h, const std::vector<RunSpec>& specs, Timer& tm) {
-  if (run_call(h, specs) != QST_OK) return -1.0;
+  if (!tm.e0 || !tm.e1 || run_call(h, specs) != QST_OK) return -1.0;
   std::vector<float> ts;
   for (int rep = 0; rep < 3; ++rep) {
-    hipEventRecord(tm.e0, h->stream);
+    if (hipEventRecord(tm.e0, h->stream) != hipSuccess) return -1.0;
     if (run_call(h, specs) != QST_OK) return -1.0;
-    hipEventRecord(tm.e1, h->stream);
-    if (hipEventSynchronize(tm.e1) != hipSuccess) return -1.0;
+    if (hipEventRecord(tm.e1, h->stream) != hipSuccess || hipEventSynchronize(tm.e1) != hipSuccess) return -1.0;
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, tm.e0, tm.e1);
+    if (hipEventElapsedTime(&ms, tm.e0, tm.e1) != hipSuccess) return -1.0;
     ts.push_back(ms);
   }
   std::sort(ts.begin(), ts.end());

@@ -24,7 +24,7 @@ struct DevBuf {
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);  // release on every path; a failure here has nothing to report to
   }
   hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 1); }
   template <typename T>
