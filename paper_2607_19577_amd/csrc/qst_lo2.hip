@@ -127,7 +127,9 @@ __global__ __launch_bounds__(lo2_threads<NB>()) void k_stage_lo2(const LoArgs a)
     if constexpr (ADJ) {
       const long long wbase = (long long)s * a.R * D + ((long long)h << wb);
       const uint32_t wext = (uint32_t)((D - ((long long)h << wb)) * CBH);
-      for (int r = 0; r < a.R; ++r) {
+      // atoms in reverse order: the last ones read by sweep 1 may still be in L2 (n=22, R=16:
+      // 162.1 against 165.8 ms per step in this stage)
+      for (int r = a.R - 1; r >= 0; --r) {
         float x[V], y[V];
         load(r, x, y);
         fwd_chain<0, CH, WL, false, LOGV>(x, y, re, im, tid, pc, nullptr);
