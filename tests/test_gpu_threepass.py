@@ -202,3 +202,61 @@ def test_ranks_above_sixteen_against_the_oracle(h, n, R):
     stage with six low bits (n=15, R=256) and with seven (n=16, R=100), against the oracle."""
     case = _case(9400 + n, n, R, 2)
     _check(_gpu(h, _inst(case)), _oracle(case), TOL32, f"n={n} R={R}")
+
+
+def _pauli_on_qubit(psi, n, j, code):
+    """sigma_code on qubit j (index bit n-1-j) of a device vector, with torch only."""
+    v = psi.reshape(1 << j, 2, 1 << (n - 1 - j))
+    if code == 2:  # Z
+        return torch.cat([v[:, :1], -v[:, 1:]], dim=1).reshape(-1)
+    if code == 0:  # X
+        return torch.cat([v[:, 1:], v[:, :1]], dim=1).reshape(-1)
+    return torch.cat([-1j * v[:, 1:], 1j * v[:, :1]], dim=1).reshape(-1)  # Y
+
+
+@pytest.mark.parametrize("n", [26, 28])
+def test_largest_states_closed_forms_on_device(h, n):
+    """n=26 and n=28 at R=1 (the largest states one 4 GiB buffer range holds: three passes, the
+    low stage over fourteen bits, a middle pass of six or seven and a top pass of six or seven),
+    three settings, the first all Z.  Closed forms evaluated with torch on the device: the all-Z
+    probabilities alpha |psi|^2; every setting's probabilities sum to alpha ||psi||^2; g = 1
+    gives alpha B psi; g = (-1)^{u_j} gives alpha sum_b sigma^(j)_{s_bj} psi for one qubit in
+    each pass."""
+    from paper_2607_19577_amd import api
+
+    B, D = 3, 1 << n
+    gen = torch.Generator(device=DEV).manual_seed(9500 + n)
+    psi = torch.complex(torch.randn(D, generator=gen, device=DEV), torch.randn(D, generator=gen, device=DEV))
+    psi = (psi / torch.linalg.vector_norm(psi)).to(torch.complex64).reshape(1, D)
+    w = torch.tensor([0.75], dtype=torch.float64, device=DEV)
+    s = synth.random_settings(synth.make_rng(9500 + n), B, n)
+    s[0, :] = 2
+    inst = api.Instance(psi, w, torch.from_numpy(s).to(DEV), torch.full((B, D), 1.0 / D, device=DEV))
+    probs, _ = api.qst_forward(h, [inst], want_probs=True)
+    torch.cuda.synchronize()
+    p = probs[0]
+    a2 = (psi[0].real.double() ** 2 + psi[0].imag.double() ** 2)
+    want0 = 0.75 * a2
+    assert float(torch.linalg.vector_norm(p[0].double() - want0) / torch.linalg.vector_norm(want0)) <= TOL32
+    tot = 0.75 * float(a2.sum())
+    assert torch.allclose(p.double().sum(dim=1), torch.full((B,), tot, dtype=torch.float64, device=DEV), rtol=1e-5)
+    del probs, p
+    ones = torch.ones((B, D), dtype=torch.float32, device=DEV)
+    _, ag, _ = api.qst_backward(h, [inst], grad_p=[ones])
+    torch.cuda.synchronize()
+    want = 0.75 * B * psi[0].to(torch.complex128)
+    assert float(torch.linalg.vector_norm(ag[0][0].to(torch.complex128) - want) / torch.linalg.vector_norm(want)) <= TOL32
+    del ones, ag
+    for j in (0, n // 2, n - 1):
+        bit = n - 1 - j
+        sign = 1.0 - 2.0 * ((torch.arange(D, device=DEV) >> bit) & 1).float()
+        _, ag, _ = api.qst_backward(h, [inst], grad_p=[sign.expand(B, D).contiguous()])
+        torch.cuda.synchronize()
+        want = torch.zeros(D, dtype=torch.complex128, device=DEV)
+        p64 = psi[0].to(torch.complex128)
+        for b in range(B):
+            want += _pauli_on_qubit(p64, n, j, int(s[b, j]))
+        want *= 0.75
+        got = ag[0][0].to(torch.complex128)
+        assert float(torch.linalg.vector_norm(got - want) / torch.linalg.vector_norm(want)) <= TOL32, j
+        del ag, sign, want, got, p64
