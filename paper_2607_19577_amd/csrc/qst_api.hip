@@ -487,8 +487,8 @@ void mark(Geometry& g, const qst_instance& in) {
   g.sparse = in.freqs_rowptr != nullptr;
   // More than ten bits above the low stage: with Pauli settings and dense data the low stage
   // takes n - 10 bits with its atoms looped (two sweeps over X), which keeps two tile passes
-  // and moves 24 B per (setting, atom) amplitude less than a middle pass (section on the
-  // three-pass schedule).  QST_LO2=0 (environment, read once) keeps the middle pass.
+  // and moves 24 B per (setting, atom) amplitude less than a middle pass would.  QST_LO2=0
+  // (environment, read once) keeps the middle pass.
   static const bool lo2_on = [] {
     const char* e = std::getenv("QST_LO2");
     return !(e && std::atoi(e) == 0);

@@ -26,7 +26,8 @@ def test_more_than_one_gpu_is_refused():
 @pytest.mark.parametrize("kernel", ["k_stage_hi_fwd", "k_stage_lo_fused", "k_stage_hi_adj"])
 def test_traffic_summaries_match_the_kernel_sources(kernel):
     """The HBM traffic in the bench line comes from profiles/ only if they were taken on these
-    sources; each stage's measured bytes are its algorithmic bytes (section on rooflines)."""
+    sources; each stage's measured bytes are its algorithmic bytes: X and W once each way, the
+    frequencies once per setting, the atoms and the gradient once per batch."""
     t = bench.read_traffic(kernel, "n20_r16_b2000")
     assert t is not None, "profiles/ were taken on other kernel sources"
     n, R, B = 20, 16, 2000
