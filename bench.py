@@ -719,6 +719,15 @@ def main():
             tms = (time.perf_counter() - t0) * 1e3
             extras[f"{name}_path_ms"] = round(tms, 1)
             extras[f"{name}_speedup_vs_plain"] = round(plain_ms / tms, 2)
+            if name.startswith("tile"):
+                # matrix-core work of the call: 16x16 complex tiles over every (setting, atom)
+                # amplitude, ceil(n/4) groups per direction, 128 flop per amplitude and group
+                # (twice that executed with split BF16 operands), against the dense peak
+                groups = -(-n // 4)
+                flop = 2 * groups * B * R * D * 128 * (2 if name == "tile_bf16" else 1)
+                tf = flop / (tms * 1e-3) / 1e12
+                extras[f"{name}_mfma"] = {"achieved": round(tf, 1), "peak": 2500.0, "unit": "TFLOP/s",
+                                          "frac": round(tf / 2500.0, 4)}
         # general local settings: three Haar 2x2 unitaries besides the Pauli bases (codes 0..5),
         # one fused backward on the same atoms and frequencies
         grng = synth.make_rng(seed + 17)
