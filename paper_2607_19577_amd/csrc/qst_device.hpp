@@ -514,6 +514,7 @@ __device__ __forceinline__ void st_cs(T x, T y, rsrc_t rs, uint32_t voff, uint32
 // lo(0) = NB - LOGV, then LOGV bits lower per step down to 0.
 template <int NB, int LOGV>
 struct Chain {
+  static constexpr int nb() { return NB; }
   static constexpr int lo(int k) {
     int l = NB - LOGV;
     for (int j = 0; j < k; ++j) l = l - LOGV > 0 ? l - LOGV : 0;

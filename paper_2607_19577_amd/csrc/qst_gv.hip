@@ -73,7 +73,7 @@ __global__ __launch_bounds__(1 << (kGvLoBits - LOGV)) void k_gv_lo(const GvArgs 
 #pragma unroll
       for (int i = 0; i < V; ++i) x[i] = xs[i], y[i] = ys[i];
       apply_phase<false, LOGV>(x, y, pos0, ym, off0);
-      fwd_chain<0, CH, false, false, LOGV>(x, y, re, im, tau, pc, nullptr);
+      fwd_chain<0, CH, false, false, LOGV, false>(x, y, re, im, tau, pc, nullptr);
       // this thread's outcomes of the chunk (final layout lo = 0)
       const float* gr = a.g + (long long)b * D + ((long long)hh << NB) + ((long long)tau << LOGV);
 #pragma unroll

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(lo2_threads<NB>()) void k_stage_lo2(const LoArgs a)
       for (int r = a.R - 1; r >= 0; --r) {
         float x[V], y[V];
         load(r, x, y);
-        fwd_chain<0, CH, WL, false, LOGV>(x, y, re, im, tid, pc, nullptr);
+        fwd_chain<0, CH, WL, false, LOGV, false>(x, y, re, im, tid, pc, nullptr);
         const float al = (float)a.alpha[r];
         float hl = 0.0f;
 #pragma unroll

@@ -259,7 +259,7 @@ __global__ __launch_bounds__((oc_threads<NB, LOGV>()), (LOGV == 5 ? 2 : 4)) void
 #pragma unroll
       for (int i = 0; i < V; ++i) bload2(x[i], y[i], rs, vo0 + abase, off0(i) * 8u);
       apply_phase<false, LOGV>(x, y, pos0, ym, off0);
-      fwd_chain<0, CH, WL, false, LOGV>(x, y, re, im, tau, pc, nullptr);
+      fwd_chain<0, CH, WL, false, LOGV, false>(x, y, re, im, tau, pc, nullptr);
       // this thread's outcomes (final layout lo = 0)
       const long long row = (long long)b * D + ((long long)tau << LOGV);
       float g[V];
@@ -278,8 +278,9 @@ __global__ __launch_bounds__((oc_threads<NB, LOGV>()), (LOGV == 5 ? 2 : 4)) void
         y[i] *= sc;
       }
       h_acc += (double)hl;
-      // (every work-group transpose ends with a barrier after its reads, so the LDS
-      // planes are free for the next transpose without one here)
+      // (the adjoint chain starts with the forward chain's last transpose reversed, which
+      // touches only positions of this wavefront; its work-group transposes end with a
+      // barrier, so the next setting's forward chain finds the planes free)
       adj_chain<NL - 1, CH, WL, false, LOGV>(x, y, re, im, tau, pc, nullptr);
       apply_phase<true, LOGV>(x, y, pos0, ym, off0);
 #pragma unroll

@@ -70,12 +70,54 @@ __device__ __forceinline__ void lds_transpose_wave(T (&x)[1 << LOGV], T (&y)[1 <
   wave_sync();
 }
 
-// Transpose of the low stage: wavefront-local (one plane per atom, re = that
-// plane) or work-group wide (separate re and im planes).
-template <bool WL, int LOGV, int LO_FROM, int LO_TO, typename T>
+// Index bits that select the wavefront of a thread in layout `lo` of a vector of 2^NB
+// amplitudes held by 2^(NB-LOGV) threads: thread bits 6 and up, which stand for index bit t
+// below lo and t + LOGV from lo on.
+template <int NB, int LOGV>
+constexpr uint32_t wave_index_bits(int lo) {
+  uint32_t m = 0;
+  for (int t = 6; t < NB - LOGV; ++t) m |= 1u << (t < lo ? t : t + LOGV);
+  return m;
+}
+
+// A work-group transpose between two layouts in which every wavefront holds the same index
+// bits: each wavefront reads back only what it wrote, so the exchange needs no barrier.
+// TAIL (the last transpose of a chain) ends with one all the same, so that whatever follows
+// the chain finds the planes free, as after a work-group transpose.
+template <int LOGV, int LO_FROM, int LO_TO, bool TAIL, typename T>
+__device__ __forceinline__ void lds_transpose_own(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau) {
+  T* rw = re + pad_base<LOGV, LO_FROM>(tau);
+  T* iw = im + pad_base<LOGV, LO_FROM>(tau);
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) {
+    rw[pad_off<LO_FROM>(i)] = x[i];
+    iw[pad_off<LO_FROM>(i)] = y[i];
+  }
+  wave_sync();
+  const T* rr = re + pad_base<LOGV, LO_TO>(tau);
+  const T* ir = im + pad_base<LOGV, LO_TO>(tau);
+#pragma unroll
+  for (int i = 0; i < (1 << LOGV); ++i) {
+    x[i] = rr[pad_off<LO_TO>(i)];
+    y[i] = ir[pad_off<LO_TO>(i)];
+  }
+  if constexpr (TAIL)
+    __syncthreads();
+  else
+    wave_sync();
+}
+
+// Transpose of a layout chain: wavefront-local (one plane per atom, re = that plane),
+// work-group wide between layouts that keep each wavefront's index bits (no barrier inside),
+// or work-group wide (separate re and im planes, barriers after the writes and the reads).
+// A work-group transpose that follows one of the second kind within a chain writes exactly
+// the positions its wavefront has just read, so it needs no barrier before its writes.
+template <bool WL, int NB, int LOGV, int LO_FROM, int LO_TO, bool TAIL, typename T>
 __device__ __forceinline__ void lo_transpose(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau) {
   if constexpr (WL)
     lds_transpose_wave<LOGV, LO_FROM, LO_TO>(x, y, re, tau);
+  else if constexpr (wave_index_bits<NB, LOGV>(LO_FROM) == wave_index_bits<NB, LOGV>(LO_TO))
+    lds_transpose_own<LOGV, LO_FROM, LO_TO, TAIL>(x, y, re, im, tau);
   else
     lds_transpose<LOGV, LO_FROM, LO_TO>(x, y, re, im, tau);
 }
@@ -90,17 +132,21 @@ constexpr uint32_t chain_mask() {
 }
 
 // Butterflies of every layout of the chain, first to last.  GEN: the general 2x2
-// matrices of the setting (um, by index bit) instead of the Pauli butterflies.
-template <int K, typename CH, bool WL, bool GEN, int LOGV, typename T>
+// matrices of the setting (um, by index bit) instead of the Pauli butterflies.  SYNC_END
+// = false leaves out the barrier that ends a chain whose last transpose keeps each
+// wavefront's index bits: allowed when every wavefront's next access to the planes is the
+// first transpose of an adjoint chain (which writes only the positions it has just read).
+template <int K, typename CH, bool WL, bool GEN, int LOGV, bool SYNC_END = true, typename T>
 __device__ __forceinline__ void fwd_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], T* re, T* im, int tau, uint64_t pc,
                                           cfptr um) {
   if constexpr (K < CH::count()) {
-    if constexpr (K > 0) lo_transpose<WL, LOGV, CH::lo(K - 1), CH::lo(K)>(x, y, re, im, tau);
+    if constexpr (K > 0)
+      lo_transpose<WL, CH::nb(), LOGV, CH::lo(K - 1), CH::lo(K), SYNC_END && K + 1 == CH::count()>(x, y, re, im, tau);
     if constexpr (GEN)
       xform_gen<LOGV, false, chain_mask<CH, K>()>(x, y, um, CH::lo(K));
     else
       xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
-    fwd_chain<K + 1, CH, WL, GEN, LOGV>(x, y, re, im, tau, pc, um);
+    fwd_chain<K + 1, CH, WL, GEN, LOGV, SYNC_END>(x, y, re, im, tau, pc, um);
   }
 }
 
@@ -114,7 +160,7 @@ __device__ __forceinline__ void adj_chain(T (&x)[1 << LOGV], T (&y)[1 << LOGV], 
   else
     xform_xz<LOGV, chain_mask<CH, K>()>(x, y, layout_codes<LOGV>(pc, CH::lo(K), CH::lo(K), CH::top(K), 0, 0));
   if constexpr (K > 0) {
-    lo_transpose<WL, LOGV, CH::lo(K), CH::lo(K - 1)>(x, y, re, im, tau);
+    lo_transpose<WL, CH::nb(), LOGV, CH::lo(K), CH::lo(K - 1), K == 1>(x, y, re, im, tau);
     adj_chain<K - 1, CH, WL, GEN, LOGV>(x, y, re, im, tau, pc, um);
   }
 }

@@ -68,12 +68,11 @@ def test_autotune_one_shape(tmp_path):
         assert c4 == c, (c4, c)
 
 
-@pytest.mark.parametrize("kind,lv", [(0, 0), (1, 5), (1, 4), (2, 0)])
-def test_every_kind_matches_oracle(kind, lv):
+@pytest.mark.parametrize("kind,lv,n", [(0, 0, 12), (1, 5, 12), (1, 4, 13), (1, 4, 14), (1, 5, 14), (2, 0, 12)])
+def test_every_kind_matches_oracle(kind, lv, n):
     from paper_2607_19577_amd import api
 
-    n = 13 if lv == 4 else 12
-    case = make_case(1210 + kind * 7 + lv, n, 16384 >> n, 24, shots=5000)  # R 2^n = 2^14: every kind applies
+    case = make_case(1210 + kind * 7 + lv + n, n, 16384 >> n, 24, shots=5000)  # R 2^n = 2^14: every kind applies
     inst = to_device(case, DEV)
     print("pinned kind", kind, "logv", lv, flush=True)
     with api.Handle(0) as h:
