@@ -80,6 +80,16 @@ constexpr uint32_t wave_index_bits(int lo) {
   return m;
 }
 
+// 2^14 amplitudes, 32 per thread (layouts 9, 4, 0): wavefronts hold index bits 6..8 in the
+// first layout and 11..13 in the other two, so only the step 9 -> 4 crosses wavefronts.
+static_assert(wave_index_bits<14, 5>(9) == 0x1C0u && wave_index_bits<14, 5>(4) == 0x3800u &&
+              wave_index_bits<14, 5>(0) == 0x3800u);
+// 16 per thread (layouts 10, 6, 2, 0): bits 6..9, then 10..13 from layout 6 on.
+static_assert(wave_index_bits<14, 4>(10) == 0x3C0u && wave_index_bits<14, 4>(6) == 0x3C00u &&
+              wave_index_bits<14, 4>(2) == 0x3C00u && wave_index_bits<14, 4>(0) == 0x3C00u);
+// One wavefront per vector (2^11 amplitudes, 32 per thread): no wavefront bits.
+static_assert(wave_index_bits<11, 5>(6) == 0u && wave_index_bits<11, 5>(0) == 0u);
+
 // A work-group transpose between two layouts in which every wavefront holds the same index
 // bits: each wavefront reads back only what it wrote, so the exchange needs no barrier.
 // TAIL (the last transpose of a chain) ends with one all the same, so that whatever follows
