@@ -598,8 +598,11 @@ __global__ __launch_bounds__(256) void k_oc_rowsum(const OcInst* __restrict__ ta
 }
 
 // Work-group (k, r): grad_r -= psi_r <psi_r, grad_r> with the inner product in FP64.
-__global__ __launch_bounds__(256) void k_oc_tangent(const OcInst* __restrict__ tab) {
-  __shared__ double red[256];
+// One work-group of 1024 threads per (instance, atom): the vector is at most 2^14 long, so
+// each thread takes at most 16 elements per pass; the dot product is summed over each
+// wavefront by a fixed butterfly of lane exchanges, then over the wavefronts in order.
+__global__ __launch_bounds__(1024) void k_oc_tangent(const OcInst* __restrict__ tab) {
+  __shared__ double red[2][16];
   const OcInst& a = tab[blockIdx.x];
   const int r = blockIdx.y;
   if (!a.tangent || r >= a.R) return;
@@ -607,14 +610,30 @@ __global__ __launch_bounds__(256) void k_oc_tangent(const OcInst* __restrict__ t
   const float2* psi = reinterpret_cast<const float2*>(a.atoms) + (long long)r * D;
   float2* grad = a.grad + (long long)r * D;
   double sre = 0.0, sim = 0.0;
-  for (long long i = threadIdx.x; i < D; i += 256) {
+  for (long long i = threadIdx.x; i < D; i += 1024) {
     const float2 p = psi[i], g = grad[i];
     sre += (double)p.x * g.x + (double)p.y * g.y;  // conj(p) g
     sim += (double)p.x * g.y - (double)p.y * g.x;
   }
-  const float dr = (float)oc_block_sum(sre, red);
-  const float di = (float)oc_block_sum(sim, red);
-  for (long long i = threadIdx.x; i < D; i += 256) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sre += __shfl_xor(sre, o);
+    sim += __shfl_xor(sim, o);
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wave] = sre;
+    red[1][wave] = sim;
+  }
+  __syncthreads();
+  double tr = 0.0, ti = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    tr += red[0][w];
+    ti += red[1][w];
+  }
+  const float dr = (float)tr;
+  const float di = (float)ti;
+  for (long long i = threadIdx.x; i < D; i += 1024) {
     const float2 p = psi[i];
     float2 g = grad[i];
     g.x -= p.x * dr - p.y * di;
@@ -775,7 +794,7 @@ hipError_t launch_oc_finish(const OcInst* tab, int count, int sum_blocks, int rm
                             hipStream_t st) {
   if (sum_blocks > 0) k_oc_sum<<<sum_blocks, kOcSumCols * kOcSumThreads, 0, st>>>(tab, count);
   if (rows) k_oc_rowsum<<<dim3(count, rmax + 1), 256, 0, st>>>(tab);
-  if (tangent) k_oc_tangent<<<dim3(count, rmax), 256, 0, st>>>(tab);
+  if (tangent) k_oc_tangent<<<dim3(count, rmax), 1024, 0, st>>>(tab);
   return hipGetLastError();
 }
 
