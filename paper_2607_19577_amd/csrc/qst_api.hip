@@ -63,6 +63,13 @@ struct qst_handle {
   // no-allocation mode (qst_backward_static): ws points at the device's static scratch
   void* static_scratch = nullptr;  // this device's copy of `scratch` (from qst_create)
   bool static_ws = false;
+  // side streams (default priority) that the classes of a multi-instance call fork onto
+  // from `stream` and join back from, through events (also under graph capture)
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kSide] = {};
+  bool side_ok = false;
 };
 
 namespace {
@@ -1194,29 +1201,52 @@ qst_status run_table(qst_handle* h, std::vector<const RunSpec*> rs, size_t* need
   }
   QST_HIP(qst::launch_oc_decode(dtab, count, dec_blocks, h->dflag, s));
   prof_end(h);
-  for (const Group& gr : groups) {
+  // The classes touch disjoint instances (their own outputs and workspace rows) and read
+  // only the decoded table, so with more than one class each runs on a side stream forked
+  // from s after the decode; s waits for all of them before the sums.  With stage timing
+  // on, everything stays on s.
+  const bool fork = groups.size() > 1 && h->side_ok && !h->prof;
+  bool used[qst_handle::kSide] = {};
+  if (fork) QST_HIP(hipEventRecord(h->fork_ev, s));
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& gr = groups[gi];
     const bool adj = rs[gr.k0]->adjoint;
+    hipStream_t gs = s;
+    if (fork) {
+      const int j = (int)(gi % qst_handle::kSide);
+      gs = h->side[j];
+      if (!used[j]) {
+        QST_HIP(hipStreamWaitEvent(gs, h->fork_ev, 0));
+        used[j] = true;
+      }
+    }
     if (gr.kind == TK_FS) {
       const int grid =
           (int)std::min<long long>(gr.itemsA, (long long)h->num_cu * fs_occ(h, gr.n, gr.RM, adj));
       prof_begin(h, PK_LO);
-      QST_HIP(qst::launch_fs_pass(gr.n, adj, dtab, gr.k0, gr.k1, gr.itemsA, gr.RM, grid, s));
+      QST_HIP(qst::launch_fs_pass(gr.n, adj, dtab, gr.k0, gr.k1, gr.itemsA, gr.RM, grid, gs));
       prof_end(h);
       continue;
     }
     if (gr.itemsF > 0) {
       const int grid = (int)std::min<long long>(gr.itemsF, (long long)h->num_cu * oc_occ(h, gr.n, gr.logv, false));
       prof_begin(h, PK_HI_FWD);
-      QST_HIP(qst::launch_oc_pass(gr.n, gr.logv, false, dtab, gr.k0, gr.k1, gr.itemsF, grid, s));
+      QST_HIP(qst::launch_oc_pass(gr.n, gr.logv, false, dtab, gr.k0, gr.k1, gr.itemsF, grid, gs));
       prof_end(h);
     }
     if (gr.itemsA > 0) {
       const int grid = (int)std::min<long long>(gr.itemsA, (long long)h->num_cu * oc_occ(h, gr.n, gr.logv, true));
       prof_begin(h, PK_LO);
-      QST_HIP(qst::launch_oc_pass(gr.n, gr.logv, true, dtab, gr.k0, gr.k1, gr.itemsA, grid, s));
+      QST_HIP(qst::launch_oc_pass(gr.n, gr.logv, true, dtab, gr.k0, gr.k1, gr.itemsA, grid, gs));
       prof_end(h);
     }
   }
+  if (fork)
+    for (int j = 0; j < qst_handle::kSide; ++j)
+      if (used[j]) {
+        QST_HIP(hipEventRecord(h->join_ev[j], h->side[j]));
+        QST_HIP(hipStreamWaitEvent(s, h->join_ev[j], 0));
+      }
   if (sum_blocks > 0 || any_rows || any_tan) {
     prof_begin(h, PK_REDUCE);
     QST_HIP(qst::launch_oc_finish(dtab, count, sum_blocks, rmax, any_rows, any_tan, s));
@@ -1505,6 +1535,12 @@ qst_status qst_create(int device, void* hip_stream, qst_handle** out) {
     return QST_ERR_DEVICE;
   }
   if (scratch_address(device, &h->static_scratch) != hipSuccess) h->static_scratch = nullptr;
+  // side streams for the classes of multi-instance calls; without them the classes run one
+  // after another on the handle's stream
+  h->side_ok = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < qst_handle::kSide && h->side_ok; ++i)
+    h->side_ok = hipStreamCreateWithFlags(&h->side[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&h->join_ev[i], hipEventDisableTiming) == hipSuccess;
   *out = h;
   return QST_OK;
 }
@@ -1524,6 +1560,11 @@ qst_status qst_destroy(qst_handle* h) {
   if (h->hflag) (void)hipHostFree(h->hflag);
   if (h->flag_ev) (void)hipEventDestroy(h->flag_ev);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  for (int i = 0; i < qst_handle::kSide; ++i) {
+    if (h->side[i]) (void)hipStreamDestroy(h->side[i]);
+    if (h->join_ev[i]) (void)hipEventDestroy(h->join_ev[i]);
+  }
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   delete h;
   return QST_OK;
 }
